@@ -1,0 +1,181 @@
+/*
+ * deam.h -- C ABI of the MI355X (gfx950) DEAM hot-path library.
+ *
+ * DEAM (dual-energy alternating minimisation) with the metal-trace data
+ * substitution of Ge et al., "A Metal Artifact Reduction Scheme For Accurate
+ * Iterative Dual-Energy CT Algorithms":
+ *   - forward model (Section 2.3, Eq. 8):
+ *       g_j(y) = sum_E I0_j(E) exp(-sum_i mu_i(E) l_i(y)),  l_i = H c_i,
+ *     with h(x,y) the exact intersection length (mm) of ray y and voxel x;
+ *   - metal trace (Section 2.1, Eqs. 2-3): T(y) = sum_x h(x,y) M(x); ray y is
+ *     corrupt when T(y) >= t and its measurement is not used;
+ *   - DEAM step: the I-divergence of Eq. 5 is minimised by alternating a
+ *     p-step on the linear family of Eqs. 9-10 (p_j = q_j d_j / g_j, and
+ *     p_j = q_j on the trace: Eq. 11 and the sentence after it) and the
+ *     component update c_i <- c_i - ln(b~_i / b^_i) / Z_i, where
+ *     b~_i = H^T sum_j sum_E mu_i p_j and b^_i = H^T sum_j sum_E mu_i q_j.
+ *
+ * Layouts (all C order, channel-major):
+ *   image     [n_ch][V],  V = nz*ny*nx, index (iz*ny + iy)*nx + ix (x fastest);
+ *             2D geometries have nz = 1.  Voxel (ix,iy,iz) covers
+ *             [x0+ix*dx, x0+(ix+1)*dx] x ... with x0 = -nx*dx/2 (grid centred
+ *             on the isocentre).
+ *   sinogram  [n_ch][R],  R = n_views*n_rows*n_cols, index (v*n_rows + r)*n_cols + k.
+ *   Ray (v,r,k): source S = (sid cos b, sid sin b, zs(v)), b = beta0 + 2 pi v /
+ *             views_per_rot, zs(v) = (v - (n_views-1)/2) feed_per_rot / views_per_rot;
+ *             end point P = S + sdd R(gamma_k) u + (0,0,zeta_r), u = -(cos b, sin b, 0),
+ *             gamma_k = (k - (n_cols-1)/2 - col_offset) dgamma,
+ *             zeta_r = (r - (n_rows-1)/2) drow_iso sdd / sid  (zeta = 0 in 2D).
+ *
+ * Precision: a plan is created MIXED (projections, energy sums and weights in
+ * FP32; objective terms, reductions and the component update in FP64) or FP64
+ * (every step in FP64).  "real" below is float for MIXED and double for FP64.
+ *
+ * Memory: every data pointer is a device pointer owned by the caller (e.g. a
+ * torch tensor), unless stated otherwise.  The plan owns only its small
+ * geometry and spectrum tables.  Calls are asynchronous on the given stream
+ * (a hipStream_t; NULL = the default stream) and enqueue nothing when they
+ * return an error.  Concurrent calls on one plan are allowed on different
+ * streams when each uses its own workspace.
+ *
+ * Errors: every function returns a deam_status; on failure deam_last_error()
+ * gives a message (thread-local).  Argument checks happen before anything is
+ * enqueued; a device fault shows up at the next synchronisation.  Input data
+ * values are not checked on the hot path.
+ */
+#ifndef DEAM_H
+#define DEAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DEAM_OK = 0,
+  DEAM_ERR_NULL = -1,        /* a required pointer is NULL */
+  DEAM_ERR_SHAPE = -2,       /* a size or channel count is out of range */
+  DEAM_ERR_GEOMETRY = -3,    /* the geometry is invalid (e.g. source inside the grid) */
+  DEAM_ERR_WORKSPACE = -4,   /* the workspace is too small */
+  DEAM_ERR_HIP = -5,         /* a HIP runtime call failed */
+  DEAM_ERR_UNSUPPORTED = -6, /* the request is valid but not supported by this build */
+  DEAM_ERR_VALUE = -7        /* a scalar argument has an invalid value */
+} deam_status;
+
+typedef enum { DEAM_FAN2D = 0, DEAM_HELICAL3D = 1 } deam_kind;
+typedef enum { DEAM_PREC_MIXED = 0, DEAM_PREC_FP64 = 1 } deam_precision;
+
+/* Weight modes of deam_poly_mean. */
+typedef enum {
+  DEAM_W_AM = 0,   /* 4 channels (w~1, w~2, w^1, w^2); objective = masked I-divergence terms */
+  DEAM_W_GRAD = 1, /* 2 channels u_i = sum_j (r_j - 1) a_ij; objective = masked NLL terms */
+  DEAM_W_VJP = 2   /* 2 channels u_i = -sum_j v_j a_ij for an upstream v_j = dloss/dg_j */
+} deam_wmode;
+
+/* Workspace queries. */
+typedef enum {
+  DEAM_OP_FORWARD = 0,
+  DEAM_OP_POLY_MEAN = 1,
+  DEAM_OP_BACKPROJECT = 2,
+  DEAM_OP_ITERATE = 3,
+  DEAM_OP_METAL_TRACE = 4
+} deam_op;
+
+typedef struct {
+  int32_t kind;                 /* deam_kind */
+  int32_t nx, ny, nz;           /* voxels; nz = 1 for DEAM_FAN2D */
+  double dx, dy, dz;            /* voxel size, mm */
+  int32_t n_views, n_rows, n_cols; /* n_rows = 1 for DEAM_FAN2D */
+  double sid, sdd;              /* source-isocentre and source-detector distances, mm */
+  double dgamma, col_offset;    /* equiangular channel pitch (rad), channel offset (cells) */
+  double drow_iso;              /* detector row pitch at the isocentre, mm (3D) */
+  double beta0, views_per_rot;  /* start angle (rad), views per 2 pi */
+  double feed_per_rot;          /* table feed per rotation, mm (0 in 2D) */
+} deam_geometry;
+
+typedef struct deam_plan deam_plan;
+
+/* Create a plan for one scanner geometry and one pair of spectra.
+ *   I0  host [2][n_energy]: photons per ray of the low and high spectrum per
+ *       energy bin (the I0_j(E) of Eq. 8; no bowtie: the same for every ray);
+ *   mu  host [2][n_energy]: basis attenuation mu_i(E) in 1/mm (Eq. 8).
+ * Bins where both spectra are zero are dropped (their terms are exactly 0).
+ * precision: deam_precision.  Copies the tables to the current device. */
+int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* I0,
+                     const double* mu, int32_t precision, deam_plan** out);
+int deam_plan_destroy(deam_plan* plan);
+/* Number of rays R and voxels V of the plan (host outputs). */
+int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels);
+/* Bytes of device workspace needed by an operation (deam_op). */
+int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes);
+
+/* Metal trace (Section 2.1, Eqs. 2-3): T(y) = sum_x h(x,y) M(x) in FP64 for
+ * both precisions, and mask[y] = (T(y) >= t).
+ *   M     [V]  uint8, non-zero = metal voxel;
+ *   mask  [R]  uint8 output;   T [R] double output, may be NULL.
+ * Workspace: deam_workspace_size(DEAM_OP_METAL_TRACE). */
+int deam_metal_trace(const deam_plan* plan, const uint8_t* M, double t, uint8_t* mask,
+                     double* T, void* ws, size_t ws_bytes, void* stream);
+
+/* Forward projection (the inner sum of Eq. 8): l[c][y] = sum_x h(x,y) c[c][x].
+ *   c  [n_ch][V] real;  l [n_ch][R] real;  n_ch = 1 or 2.
+ * Workspace: deam_workspace_size(DEAM_OP_FORWARD). */
+int deam_forward(const deam_plan* plan, const void* c, int32_t n_ch, void* l, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Per-ray polyenergetic mean (Eq. 8) with the metal-trace substitution
+ * (Eq. 11: p = q where mask = 1) and the weights that feed the backprojection.
+ *   l     [2][R] real   line integrals of the two components;
+ *   d     [2][R] float  measured counts of the low and high spectrum;
+ *   mask  [R]    uint8  corrupt rays (NULL = none);
+ *   mode  deam_wmode;
+ *   v     [2][R] real   upstream dloss/dg (DEAM_W_VJP only, else NULL);
+ *   w     [4][R] (AM) or [2][R] real output;
+ *   g     [2][R] real output, may be NULL;
+ *   obj   device double scalar output, may be NULL: the sum over rays of the
+ *         masked I-divergence terms (AM) or masked NLL terms g - d ln g (GRAD).
+ * Per ray: q_j(E) = I0_j(E) exp(-mu_1 l_1 - mu_2 l_2), g_j = sum_E q_j,
+ * a_ij = sum_E mu_i q_j, r_j = d_j/g_j off the trace and 1 on it;
+ * AM: w~_i = sum_j r_j a_ij, w^_i = sum_j a_ij.
+ * Workspace: deam_workspace_size(DEAM_OP_POLY_MEAN). */
+int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const uint8_t* mask,
+                   int32_t mode, const void* v, void* w, void* g, double* obj, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Backprojection with the transpose of the forward operator:
+ * b[c][x] = sum_y h(x,y) w[c][y].   w [n_ch][R] real; b [n_ch][V] real; n_ch = 1, 2 or 4.
+ * Accumulation is exact integer (fixed point) per voxel, so results are
+ * bitwise reproducible.  Workspace: deam_workspace_size(DEAM_OP_BACKPROJECT). */
+int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Component update: for each voxel and i = 1, 2, where b~_i > 0 and b^_i > 0,
+ * c_i <- c_i - ln(b~_i / b^_i) / Z_i (FP64); other voxels are unchanged.
+ *   c64  [2][V] double, updated in place;
+ *   b    [4][V] real (b~1, b~2, b^1, b^2) from deam_backproject;
+ *   Z    host [2] double, > 0;
+ *   c_proj [2][V] real output copy of c64 in the plan precision, may be NULL. */
+int deam_update(const deam_plan* plan, double* c64, void* c_proj, const void* b,
+                const double* Z, void* stream);
+
+/* n_iter DEAM iterations on one stream with no host synchronisation:
+ * forward projection + poly-mean (AM), backprojection, update.
+ *   c64   [2][V] double, updated in place;
+ *   d     [2][R] float counts;  mask [R] uint8 or NULL;  Z host [2];
+ *   obj_hist  device [n_iter] double or NULL: obj_hist[k] = masked
+ *             I-divergence (Eq. 5 restricted to T < t) at the iterate c^k
+ *             entering iteration k.
+ * Workspace: deam_workspace_size(DEAM_OP_ITERATE). */
+int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                 const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* deam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEAM_H */

@@ -1,0 +1,416 @@
+/*
+ * FP64 CPU oracle for the DEAM hot path with metal-trace data substitution.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it; the product path never
+ * does.  It shares no source, header or table with the GPU library.
+ *
+ * What it computes (paper: Ge et al., "A Metal Artifact Reduction Scheme For
+ * Accurate Iterative Dual-Energy CT Algorithms"):
+ *   - system operator h(x,y): exact intersection length of ray y with voxel x
+ *     (Section 2.3, the operator inside Eq. 8), by Siddon's method: all
+ *     crossings of the ray with the grid planes, merged in order, each
+ *     consecutive pair giving one voxel (found from the midpoint) and one
+ *     length;
+ *   - metal trace T(y) = sum_x h(x,y) M(x) and the corrupt-ray test
+ *     T(y) >= t (Section 2.1, Eqs. 2-3);
+ *   - forward model g_j(y) = sum_E I0_j(E) exp(-sum_i mu_i(E) l_i(y)) with
+ *     l_i = H c_i (Section 2.3, Eq. 8);
+ *   - the linear-family split of the I-divergence (Section 2.3, Eqs. 9-10)
+ *     with p_j = q_j on the metal trace (Section 2.3, Eq. 11 and the sentence
+ *     that follows it) and p_j = q_j d_j / g_j elsewhere;
+ *   - the alternating-minimisation component update
+ *     c_i <- c_i - ln(b~_i / b^_i) / Z_i, where b~_i and b^_i back-project the
+ *     energy sums of mu_i p_j and mu_i q_j (the DEAM step the paper cites to
+ *     O'Sullivan and Benac; derived from Eqs. 5, 8, 9-10);
+ *   - the masked I-divergence of Eq. 5 and the Poisson negative
+ *     log-likelihood with its gradient b~ - b^.
+ * Everything is FP64; ray sums and energy sums use Neumaier compensation.
+ */
+#include "deam_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ----------------------------------------------------------------------- */
+/* Geometry: the scanner convention of the workloads.                       */
+/* ----------------------------------------------------------------------- */
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
+
+long orc_n_rays(const orc_geom* g) { return (long)g->n_views * g->n_rows * g->n_cols; }
+long orc_n_voxels(const orc_geom* g) { return (long)g->nx * g->ny * (g->kind == ORC_HELICAL3D ? g->nz : 1); }
+
+void orc_ray(const orc_geom* g, long ray, double S[3], double P[3]) {
+  long k = ray % g->n_cols;
+  long r = (ray / g->n_cols) % g->n_rows;
+  long v = ray / ((long)g->n_cols * g->n_rows);
+  double beta = g->beta0 + 2.0 * M_PI * (double)v / g->views_per_rot;
+  double cb = cos(beta), sb = sin(beta);
+  double gam = ((double)k - 0.5 * (g->n_cols - 1) - g->col_offset) * g->dgamma;
+  double cg = cos(gam), sg = sin(gam);
+  double ux = -cb, uy = -sb;
+  double dirx = cg * ux - sg * uy, diry = sg * ux + cg * uy;
+  double zs = 0.0, zeta = 0.0;
+  if (g->kind == ORC_HELICAL3D) {
+    zs = ((double)v - 0.5 * (g->n_views - 1)) * g->feed_per_rot / g->views_per_rot;
+    zeta = ((double)r - 0.5 * (g->n_rows - 1)) * g->drow_iso * g->sdd / g->sid;
+  }
+  S[0] = g->sid * cb; S[1] = g->sid * sb; S[2] = zs;
+  P[0] = S[0] + g->sdd * dirx; P[1] = S[1] + g->sdd * diry; P[2] = zs + zeta;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Siddon's method on the grid, restricted to the voxel sub-box [lo, hi).   */
+/* ----------------------------------------------------------------------- */
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+int orc_siddon(const orc_geom* g, const double S[3], const double P[3],
+               const int lo[3], const int hi[3], long* idx, double* len, int cap,
+               double* scratch) {
+  int is3d = (g->kind == ORC_HELICAL3D);
+  int naxes = is3d ? 3 : 2;
+  int n[3] = {g->nx, g->ny, is3d ? g->nz : 1};
+  double dlt[3] = {g->dx, g->dy, g->dz};
+  double org[3];
+  for (int a = 0; a < 3; ++a) org[a] = -0.5 * n[a] * dlt[a];
+  double D[3] = {P[0] - S[0], P[1] - S[1], is3d ? P[2] - S[2] : 0.0};
+  double L = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+
+  /* ray parameter range inside the sub-box (and on the segment S..P) */
+  double amin = 0.0, amax = 1.0;
+  for (int a = 0; a < naxes; ++a) {
+    double p0 = org[a] + lo[a] * dlt[a], p1 = org[a] + hi[a] * dlt[a];
+    double s = (a < 2 || is3d) ? S[a] : 0.0;
+    if (D[a] == 0.0) {
+      if (!(s >= p0 && s < p1)) return 0;
+      continue;
+    }
+    double t0 = (p0 - s) / D[a], t1 = (p1 - s) / D[a];
+    if (t0 > t1) { double t = t0; t0 = t1; t1 = t; }
+    if (t0 > amin) amin = t0;
+    if (t1 < amax) amax = t1;
+  }
+  if (!(amax > amin)) return 0;
+
+  /* all plane crossings strictly inside (amin, amax) */
+  int m = 0;
+  scratch[m++] = amin;
+  for (int a = 0; a < naxes; ++a) {
+    if (D[a] == 0.0) continue;
+    double s = S[a];
+    /* planes whose coordinate lies between the ray's coordinates at amin and
+       amax (widened by one plane; the strict test below decides) */
+    double xa = s + amin * D[a], xb = s + amax * D[a];
+    if (xa > xb) { double t = xa; xa = xb; xb = t; }
+    int i0 = (int)floor((xa - org[a]) / dlt[a]) - 1;
+    int i1 = (int)ceil((xb - org[a]) / dlt[a]) + 1;
+    if (i0 < lo[a] + 1) i0 = lo[a] + 1;
+    if (i1 > hi[a] - 1) i1 = hi[a] - 1;
+    for (int i = i0; i <= i1; ++i) {
+      double al = (org[a] + i * dlt[a] - s) / D[a];
+      if (al > amin && al < amax) scratch[m++] = al;
+    }
+  }
+  scratch[m++] = amax;
+  qsort(scratch, (size_t)m, sizeof(double), cmp_double);
+
+  int cnt = 0;
+  for (int q = 0; q + 1 < m; ++q) {
+    double a0 = scratch[q], a1 = scratch[q + 1];
+    if (!(a1 > a0)) continue;                       /* coincident crossings */
+    double am = 0.5 * (a0 + a1);
+    int iv[3] = {0, 0, 0};
+    int ok = 1;
+    for (int a = 0; a < naxes; ++a) {
+      double x = S[a] + am * D[a];
+      iv[a] = (int)floor((x - org[a]) / dlt[a]);
+      if (iv[a] < lo[a]) iv[a] = lo[a];
+      if (iv[a] >= hi[a]) iv[a] = hi[a] - 1;
+      if (iv[a] < 0 || iv[a] >= n[a]) ok = 0;
+    }
+    if (!ok) continue;
+    if (cnt >= cap) return -1;
+    idx[cnt] = ((long)iv[2] * n[1] + iv[1]) * n[0] + iv[0];
+    len[cnt] = (a1 - a0) * L;
+    ++cnt;
+  }
+  return cnt;
+}
+
+static int max_segments(const orc_geom* g) {
+  int is3d = (g->kind == ORC_HELICAL3D);
+  return g->nx + g->ny + (is3d ? g->nz : 1) + 8;
+}
+
+int orc_siddon_ray(const orc_geom* g, const double S[3], const double P[3],
+                   long* idx, double* len, int cap) {
+  int lo[3] = {0, 0, 0};
+  int hi[3] = {g->nx, g->ny, g->kind == ORC_HELICAL3D ? g->nz : 1};
+  double* scratch = (double*)malloc(sizeof(double) * (size_t)(max_segments(g) + 4));
+  int c = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
+  free(scratch);
+  return c;
+}
+
+/* Neumaier compensated accumulation */
+typedef struct { double s, c; } nsum;
+static inline void nadd(nsum* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static inline double nval(const nsum* a) { return a->s + a->c; }
+
+/* ----------------------------------------------------------------------- */
+/* Forward projection l_k(y) = sum_x h(x,y) img_k(x)                        */
+/* ----------------------------------------------------------------------- */
+
+void orc_forward(const orc_geom* g, int nch, const double* img, double* sino) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  int cap = max_segments(g);
+  int lo[3] = {0, 0, 0};
+  int hi[3] = {g->nx, g->ny, g->kind == ORC_HELICAL3D ? g->nz : 1};
+#pragma omp parallel
+  {
+    long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
+    double* len = (double*)malloc(sizeof(double) * (size_t)cap);
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+#pragma omp for schedule(dynamic, 256)
+    for (long y = 0; y < R; ++y) {
+      double S[3], P[3];
+      orc_ray(g, y, S, P);
+      int n = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
+      for (int k = 0; k < nch; ++k) {
+        nsum acc = {0.0, 0.0};
+        for (int q = 0; q < n; ++q) nadd(&acc, len[q] * img[(long)k * V + idx[q]]);
+        sino[(long)k * R + y] = nval(&acc);
+      }
+    }
+    free(idx); free(len); free(scratch);
+  }
+}
+
+/* Forward projection of a subset of rays (for sampled checks at full size). */
+void orc_forward_rays(const orc_geom* g, int nch, const double* img, long n_sel,
+                      const long* rays, double* out /*[nch][n_sel]*/) {
+  long V = orc_n_voxels(g);
+  int cap = max_segments(g);
+  int lo[3] = {0, 0, 0};
+  int hi[3] = {g->nx, g->ny, g->kind == ORC_HELICAL3D ? g->nz : 1};
+#pragma omp parallel
+  {
+    long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
+    double* len = (double*)malloc(sizeof(double) * (size_t)cap);
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+#pragma omp for schedule(dynamic, 64)
+    for (long s = 0; s < n_sel; ++s) {
+      double S[3], P[3];
+      orc_ray(g, rays[s], S, P);
+      int n = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
+      for (int k = 0; k < nch; ++k) {
+        nsum acc = {0.0, 0.0};
+        for (int q = 0; q < n; ++q) nadd(&acc, len[q] * img[(long)k * V + idx[q]]);
+        out[(long)k * n_sel + s] = nval(&acc);
+      }
+    }
+    free(idx); free(len); free(scratch);
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Backprojection img_k(x) = sum_y h(x,y) sino_k(y): the transpose of the   */
+/* forward projection.  Each task owns a band of rows iy and walks every    */
+/* ray clipped to that band, so the sums are deterministic without atomics. */
+/* ----------------------------------------------------------------------- */
+
+void orc_backproject(const orc_geom* g, int nch, const double* sino, double* img) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  int cap = max_segments(g);
+  int band = 4;
+  int nbands = (g->ny + band - 1) / band;
+  memset(img, 0, sizeof(double) * (size_t)(nch * V));
+#pragma omp parallel
+  {
+    long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
+    double* len = (double*)malloc(sizeof(double) * (size_t)cap);
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+#pragma omp for schedule(dynamic, 1)
+    for (int b = 0; b < nbands; ++b) {
+      int lo[3] = {0, b * band, 0};
+      int hi[3] = {g->nx, (b + 1) * band < g->ny ? (b + 1) * band : g->ny,
+                   g->kind == ORC_HELICAL3D ? g->nz : 1};
+      for (long y = 0; y < R; ++y) {
+        double S[3], P[3];
+        orc_ray(g, y, S, P);
+        int n = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
+        for (int k = 0; k < nch; ++k) {
+          double w = sino[(long)k * R + y];
+          if (w == 0.0) continue;
+          for (int q = 0; q < n; ++q) img[(long)k * V + idx[q]] += len[q] * w;
+        }
+      }
+    }
+    free(idx); free(len); free(scratch);
+  }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Per-ray polyenergetic mean with metal-trace substitution.                */
+/* ----------------------------------------------------------------------- */
+
+void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
+                   const double* l, const double* d, const unsigned char* mask,
+                   int mode, const double* v, double* w, double* gout, double* obj) {
+#pragma omp parallel for schedule(static)
+  for (long y = 0; y < R; ++y) {
+    double l1 = l[y], l2 = l[R + y];
+    nsum gs[2] = {{0, 0}, {0, 0}};
+    nsum as[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};   /* as[i][j] */
+    for (int e = 0; e < nE; ++e) {
+      double mu1 = mu[e], mu2 = mu[nE + e];
+      double ex = exp(-(mu1 * l1 + mu2 * l2));
+      for (int j = 0; j < 2; ++j) {
+        double q = I0[j * nE + e] * ex;                     /* q_j(y,E) */
+        nadd(&gs[j], q);
+        nadd(&as[0][j], mu1 * q);
+        nadd(&as[1][j], mu2 * q);
+      }
+    }
+    double gj[2] = {nval(&gs[0]), nval(&gs[1])};
+    double a[2][2] = {{nval(&as[0][0]), nval(&as[0][1])}, {nval(&as[1][0]), nval(&as[1][1])}};
+    int metal = mask ? (mask[y] != 0) : 0;
+    /* r_j = d_j/g_j off the trace, 1 on it (p = q there); r_j*a_ij := 0 if g_j == 0 */
+    double ra[2][2];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        double dj = d[(long)j * R + y];
+        if (metal) ra[i][j] = a[i][j];
+        else ra[i][j] = gj[j] > 0.0 ? (dj / gj[j]) * a[i][j] : 0.0;
+      }
+    double term = 0.0;
+    if (mode == ORC_W_AM) {
+      for (int i = 0; i < 2; ++i) {
+        w[(long)i * R + y] = ra[i][0] + ra[i][1];            /* w~_i */
+        w[(long)(2 + i) * R + y] = a[i][0] + a[i][1];        /* w^_i */
+      }
+      if (!metal)
+        for (int j = 0; j < 2; ++j) {
+          double dj = d[(long)j * R + y], g = gj[j];
+          if (!(g > 0.0)) continue;
+          term += (dj > 0.0 ? dj * log(dj / g) : 0.0) - dj + g;
+        }
+    } else if (mode == ORC_W_GRAD) {
+      for (int i = 0; i < 2; ++i)
+        w[(long)i * R + y] = (ra[i][0] - a[i][0]) + (ra[i][1] - a[i][1]);
+      if (!metal)
+        for (int j = 0; j < 2; ++j) {
+          double dj = d[(long)j * R + y], g = gj[j];
+          if (!(g > 0.0)) continue;
+          term += g - (dj > 0.0 ? dj * log(g) : 0.0);
+        }
+    } else { /* ORC_W_VJP: u_i = -sum_j v_j a_ij, with v_j = dloss/dg_j */
+      for (int i = 0; i < 2; ++i)
+        w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][1]);
+    }
+    if (gout) { gout[y] = gj[0]; gout[R + y] = gj[1]; }
+    if (obj) obj[y] = term;
+  }
+}
+
+double orc_sum(long n, const double* x) {
+  nsum s = {0.0, 0.0};
+  for (long i = 0; i < n; ++i) nadd(&s, x[i]);
+  return nval(&s);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Component update c_i <- c_i - ln(b~_i / b^_i) / Z_i where both are > 0.  */
+/* ----------------------------------------------------------------------- */
+
+void orc_update(long V, const double* b, const double Z[2], double* c) {
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < V; ++x)
+    for (int i = 0; i < 2; ++i) {
+      double bt = b[(long)i * V + x], bh = b[(long)(2 + i) * V + x];
+      if (bt > 0.0 && bh > 0.0) c[(long)i * V + x] -= log(bt / bh) / Z[i];
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Metal trace and corrupt-ray mask                                          */
+/* ----------------------------------------------------------------------- */
+
+void orc_metal_trace(const orc_geom* g, const unsigned char* M, double t,
+                     unsigned char* mask, double* T) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  double* img = (double*)malloc(sizeof(double) * (size_t)V);
+  for (long x = 0; x < V; ++x) img[x] = M[x] ? 1.0 : 0.0;
+  double* tr = T ? T : (double*)malloc(sizeof(double) * (size_t)R);
+  orc_forward(g, 1, img, tr);
+  for (long y = 0; y < R; ++y) mask[y] = tr[y] >= t ? 1 : 0;
+  if (!T) free(tr);
+  free(img);
+}
+
+/* ----------------------------------------------------------------------- */
+/* DEAM iterations                                                           */
+/* ----------------------------------------------------------------------- */
+
+int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
+                const double* d, const unsigned char* mask, const double Z[2],
+                int n_iter, double* c, double* obj_hist) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  double* b = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  if (!l || !w || !obj || !b) { free(l); free(w); free(obj); free(b); return -1; }
+  for (int k = 0; k < n_iter; ++k) {
+    orc_forward(g, 2, c, l);
+    orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_AM, NULL, w, NULL, obj);
+    if (obj_hist) obj_hist[k] = orc_sum(R, obj);
+    orc_backproject(g, 4, w, b);
+    orc_update(V, b, Z, c);
+  }
+  free(l); free(w); free(obj); free(b);
+  return 0;
+}
+
+/* Objective only: masked I-divergence (mode AM) or NLL (mode GRAD) at c. */
+double orc_objective(const orc_geom* g, int nE, const double* I0, const double* mu,
+                     const double* d, const unsigned char* mask, const double* c, int mode) {
+  long R = orc_n_rays(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  orc_forward(g, 2, c, l);
+  orc_poly_mean(R, nE, I0, mu, l, d, mask, mode, NULL, w, NULL, obj);
+  double s = orc_sum(R, obj);
+  free(l); free(w); free(obj);
+  return s;
+}
+
+/* Negative log-likelihood L(c) and its gradient H^T u (u from GRAD mode). */
+double orc_nll_grad(const orc_geom* g, int nE, const double* I0, const double* mu,
+                    const double* d, const unsigned char* mask, const double* c,
+                    double* grad) {
+  long R = orc_n_rays(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* u = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  orc_forward(g, 2, c, l);
+  orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_GRAD, NULL, u, NULL, obj);
+  double s = orc_sum(R, obj);
+  if (grad) orc_backproject(g, 2, u, grad);
+  free(l); free(u); free(obj);
+  return s;
+}

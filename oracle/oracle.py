@@ -1,0 +1,217 @@
+"""ctypes front end of the FP64 CPU oracle (deam_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The GPU library never calls it.
+
+Each function mirrors one step of the DEAM hot path:
+    forward      l = H c                      (Eq. 8, the inner sum over voxels)
+    backproject  b = H^T w                    (transpose of the same h)
+    poly_mean    per-ray energy sums, weights and objective terms
+                 (Eq. 8; Eqs. 9-10; Eq. 11 substitution p = q on the trace)
+    update       c_i <- c_i - ln(b~_i / b^_i) / Z_i
+    iterate      the DEAM loop with the masked I-divergence history (Eq. 5)
+    metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+W_AM, W_GRAD, W_VJP = 0, 1, 2
+
+
+class OrcGeom(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("n_views", C.c_int), ("n_rows", C.c_int), ("n_cols", C.c_int),
+                ("sid", C.c_double), ("sdd", C.c_double), ("dgamma", C.c_double),
+                ("col_offset", C.c_double), ("drow_iso", C.c_double),
+                ("beta0", C.c_double), ("views_per_rot", C.c_double),
+                ("feed_per_rot", C.c_double)]
+
+
+def build(force=False):
+    """Compile liboracle.so with gcc (FP64, OpenMP, no fast-math)."""
+    src = os.path.join(_HERE, "deam_oracle.c")
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
+                           "-shared", "-fno-fast-math", "-ffp-contract=off", "-o", tmp,
+                           src, "-lm"])
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = np.ctypeslib.ndpointer
+        d1 = P(dtype=np.float64, flags="C_CONTIGUOUS")
+        u1 = P(dtype=np.uint8, flags="C_CONTIGUOUS")
+        i1 = P(dtype=np.int64, flags="C_CONTIGUOUS")
+        G = C.POINTER(OrcGeom)
+        L.orc_num_threads.restype = C.c_int
+        L.orc_ray.argtypes = [G, C.c_long, d1, d1]
+        L.orc_siddon_ray.argtypes = [G, d1, d1, i1, d1, C.c_int]
+        L.orc_siddon_ray.restype = C.c_int
+        L.orc_forward.argtypes = [G, C.c_int, d1, d1]
+        L.orc_forward_rays.argtypes = [G, C.c_int, d1, C.c_long, i1, d1]
+        L.orc_backproject.argtypes = [G, C.c_int, d1, d1]
+        L.orc_poly_mean.argtypes = [C.c_long, C.c_int, d1, d1, d1, d1, C.c_void_p, C.c_int,
+                                    C.c_void_p, d1, C.c_void_p, C.c_void_p]
+        L.orc_sum.argtypes = [C.c_long, d1]
+        L.orc_sum.restype = C.c_double
+        L.orc_update.argtypes = [C.c_long, d1, d1, d1]
+        L.orc_metal_trace.argtypes = [G, u1, C.c_double, u1, C.c_void_p]
+        L.orc_iterate.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
+        L.orc_iterate.restype = C.c_int
+        L.orc_objective.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int]
+        L.orc_objective.restype = C.c_double
+        L.orc_nll_grad.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_void_p]
+        L.orc_nll_grad.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def geom_struct(g):
+    return OrcGeom(g.kind, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.n_views, g.n_rows,
+                   g.n_cols, g.sid, g.sdd, g.dgamma, g.col_offset, g.drow_iso, g.beta0,
+                   g.views_per_rot, g.feed_per_rot)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def ray(g, index):
+    S, P = np.zeros(3), np.zeros(3)
+    lib().orc_ray(C.byref(geom_struct(g)), index, S, P)
+    return S, P
+
+
+def siddon(g, S, P):
+    """(voxel indices, lengths) of one ray S->P through the grid of g."""
+    cap = g.nx + g.ny + g.nz + 16
+    idx = np.zeros(cap, dtype=np.int64)
+    ln = np.zeros(cap)
+    n = lib().orc_siddon_ray(C.byref(geom_struct(g)), _f64(S), _f64(P), idx, ln, cap)
+    if n < 0:
+        raise RuntimeError("siddon capacity exceeded")
+    return idx[:n].copy(), ln[:n].copy()
+
+
+def forward(g, img):
+    img = _f64(img)
+    nch = img.size // g.n_voxels
+    out = np.zeros(nch * g.n_rays)
+    lib().orc_forward(C.byref(geom_struct(g)), nch, img.reshape(-1), out)
+    return out.reshape(nch, g.n_rays)
+
+
+def forward_rays(g, img, rays):
+    img = _f64(img)
+    rays = np.ascontiguousarray(rays, dtype=np.int64)
+    nch = img.size // g.n_voxels
+    out = np.zeros(nch * len(rays))
+    lib().orc_forward_rays(C.byref(geom_struct(g)), nch, img.reshape(-1), len(rays), rays, out)
+    return out.reshape(nch, len(rays))
+
+
+def backproject(g, sino):
+    sino = _f64(sino)
+    nch = sino.size // g.n_rays
+    out = np.zeros(nch * g.n_voxels)
+    lib().orc_backproject(C.byref(geom_struct(g)), nch, sino.reshape(-1), out)
+    return out.reshape(nch, g.n_voxels)
+
+
+def poly_mean(I0, mu, l, d, mask=None, mode=W_AM, v=None):
+    """Per-ray weights, expected counts g and objective terms.
+
+    mode W_AM  : w (4, R) = (w~1, w~2, w^1, w^2); obj = masked I-divergence terms
+    mode W_GRAD: w (2, R) = u_i = sum_j (r_j - 1) a_ij; obj = NLL terms g - d ln g
+    mode W_VJP : w (2, R) = -sum_j v_j a_ij
+    """
+    I0, mu, l, d = _f64(I0), _f64(mu), _f64(l), _f64(d)
+    R = l.shape[-1]
+    nE = I0.shape[-1]
+    nw = 4 if mode == W_AM else 2
+    w = np.zeros(nw * R)
+    g = np.zeros(2 * R)
+    obj = np.zeros(R)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    vv = None if v is None else _f64(v)
+    lib().orc_poly_mean(R, nE, I0.reshape(-1), mu.reshape(-1), l.reshape(-1), d.reshape(-1),
+                        _ptr(m), mode, _ptr(vv), w, g.ctypes.data_as(C.c_void_p),
+                        obj.ctypes.data_as(C.c_void_p))
+    return w.reshape(nw, R), g.reshape(2, R), obj
+
+
+def total(x):
+    x = _f64(x).reshape(-1)
+    return lib().orc_sum(x.size, x)
+
+
+def update(b, Z, c):
+    b, c = _f64(b), _f64(c).copy()
+    V = c.shape[-1]
+    lib().orc_update(V, b.reshape(-1), _f64(Z), c.reshape(-1))
+    return c
+
+
+def metal_trace(g, M, t):
+    M = np.ascontiguousarray(M, dtype=np.uint8).reshape(-1)
+    mask = np.zeros(g.n_rays, dtype=np.uint8)
+    T = np.zeros(g.n_rays)
+    lib().orc_metal_trace(C.byref(geom_struct(g)), M, float(t), mask, T.ctypes.data_as(C.c_void_p))
+    return mask, T
+
+
+def iterate(g, I0, mu, d, mask, Z, c0, n_iter):
+    """Run n_iter DEAM iterations from c0; returns (c, objective history)."""
+    c = _f64(c0).copy()
+    hist = np.zeros(max(n_iter, 1))
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().orc_iterate(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                           _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
+                           n_iter, c.reshape(-1), hist.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle iterate allocation failed")
+    return c, hist[:n_iter]
+
+
+def objective(g, I0, mu, d, mask, c, mode=W_AM):
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    return lib().orc_objective(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                               _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m),
+                               _f64(c).reshape(-1), mode)
+
+
+def nll_grad(g, I0, mu, d, mask, c):
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    grad = np.zeros(2 * g.n_voxels)
+    L = lib().orc_nll_grad(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                           _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m),
+                           _f64(c).reshape(-1), grad.ctypes.data_as(C.c_void_p))
+    return L, grad.reshape(2, g.n_voxels)

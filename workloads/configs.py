@@ -1,0 +1,194 @@
+"""The synthetic DEAM workloads and their seeded inputs.
+
+Each workload stands in for the paper's scanner and patient data (Section 3:
+a water phantom with steel rods on a Philips Brilliance Big Bore, and a
+clinical helical head-and-neck scan with 816 channels and 16 x 0.75 mm
+collimation), which are not available.  The shapes follow those scans:
+816-channel fan-beam and 16-row helical geometries, ~1 mm voxels, a
+water-equivalent body with bone and titanium/steel implants, and 90/140 kVp
+spectra with 1-keV bins from 20 to 140 keV.
+
+``make_inputs(name)`` returns a dict with
+    geom        Geometry
+    I0, mu      (2, n_energy) spectra (photons per ray) and basis attenuation (1/mm)
+    d           (2, n_rays) float32 Poisson counts (low, high)
+    gbar        (2, n_rays) float64 expected counts of the continuous phantom
+    metal       uint8 image, 1 where >= half of the voxel is metal
+    t           metal-trace threshold (mm of metal path)
+    c0          (2, n_voxels) float64 initial basis images (cold start)
+    Z           (2,) float64 normalisers of the surrogate update
+    n_iter      iteration count of the workload
+"""
+from __future__ import annotations
+
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from . import geometry as G
+from .physics import ENERGY_KEV, basis_mu, spectra, water_in_basis
+from .phantoms import (EllipticCylinder as E, Cylinder, MaterialPhantom,
+                       metal_fraction, random_blobs, voxel_centres)
+
+
+def geometry_for(name: str) -> G.Geometry:
+    if name == "fan128":        # 128^2 at 1 mm, 180 views over 360 deg, 256 channels
+        return G.fan2d(128, 1.0, 180, 256)
+    if name == "fan512":        # 512^2 at 0.98 mm, 984 views, 816 channels
+        return G.fan2d(512, 0.98, 984, 816)
+    if name == "helical":       # 512^2 x 64, 16 x 816 detector, 1152 views/rot, 4 rot, pitch 0.5
+        return G.helical3d(512, 0.98, 64, 1.0, 16, 816, 1152, 4, 0.5, 4.0 / 3.0)
+    if name == "fan256":        # 256^2 at 1 mm, 360 views x 512 channels
+        return G.fan2d(256, 1.0, 360, 512)
+    if name == "fan64":         # small fan-beam case for quick checks
+        return G.fan2d(64, 1.0, 64, 96)
+    if name == "helical_small":  # small helical case: 64^2 x 16, 4 rows x 96 channels
+        return G.helical3d(64, 1.0, 16, 1.0, 4, 96, 48, 2, 0.75, 2.0)
+    raise KeyError(name)
+
+
+WORKLOADS = {
+    # name: (I0, seed, iterations)
+    "fan128": (1e5, 1, 20),
+    "fan512": (2e5, 2, 50),
+    "helical": (2e5, 3, 30),
+    "fan256": (1e5, 40, 20),
+    "fan64": (1e5, 11, 20),
+    "helical_small": (1e5, 13, 10),
+}
+
+
+def phantom_for(name: str) -> MaterialPhantom:
+    if name in ("fan128", "fan64"):
+        s = 1.0 if name == "fan128" else 0.5
+        return MaterialPhantom([
+            E(0, 0, 50 * s, 50 * s, "water", "air"),
+            E(25 * s, 0, 7.5 * s, 7.5 * s, "bone", "water"),
+            E(-25 * s, 0, 7.5 * s, 7.5 * s, "bone", "water"),
+            E(0, 25 * s, 3 * s, 3 * s, "titanium", "water"),
+        ])
+    if name == "fan512":
+        objs = [E(0, 0, 200, 140, "fat", "air"), E(0, 0, 190, 130, "water", "fat"),
+                E(0, -80, 35, 25, "bone", "water", theta=0.1)]
+        for sx in (-1, 1):
+            objs += [E(sx * 95, 0, 30, 30, "cortical_bone", "water"),
+                     E(sx * 95, 0, 24, 24, "trabecular_bone", "cortical_bone"),
+                     E(sx * 95, 0, 10, 8, "steel", "trabecular_bone", theta=sx * 0.3)]
+        return MaterialPhantom(objs)
+    if name in ("helical", "helical_small"):
+        s = 1.0 if name == "helical" else 0.12
+        zl, zh = -32.0 * (1.0 if name == "helical" else 0.25), 32.0 * (1.0 if name == "helical" else 0.25)
+        objs = [E(0, 0, 180 * s, 130 * s, "fat", "air", zlo=zl, zhi=zh),
+                E(0, 0, 170 * s, 120 * s, "water", "fat", zlo=zl, zhi=zh),
+                E(0, -20 * s, 24 * s, 24 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
+                E(0, -20 * s, 22 * s, 22 * s, "trabecular_bone", "cortical_bone", zlo=zl, zhi=zh),
+                E(0, -55 * s, 20 * s, 14 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
+                E(0, -55 * s, 9 * s, 7 * s, "water", "cortical_bone", zlo=zl, zhi=zh)]
+        ang = math.radians(15.0)
+        zpos = (-12.0, 12.0) if name == "helical" else (-3.0, 3.0)
+        for sx in (-1, 1):
+            d = (-sx * math.sin(ang), math.cos(ang), 0.0)
+            for z in zpos:
+                start = (sx * 18.0 * s, -75.0 * s, z)
+                half = 22.5 * s
+                c = (start[0] + half * d[0], start[1] + half * d[1], z)
+                objs.append(Cylinder(c, d, max(2.5 * s, 1.0), half, "titanium", "water"))
+        return MaterialPhantom(objs)
+    raise KeyError(name)
+
+
+def _views_chunks(n_views, per):
+    return [np.arange(a, min(a + per, n_views)) for a in range(0, n_views, per)]
+
+
+def expected_counts(geom, phantom, I0, threads=None):
+    """Expected counts (2, n_rays) of the continuous phantom, float64."""
+    if isinstance(phantom, MaterialPhantom):
+        mu_t = phantom.mu_table()
+        lengths = phantom.path_lengths
+    else:
+        mu_t = basis_mu()
+        lengths = phantom.basis_line_integrals
+    keep = I0.sum(axis=0) > 0
+    mu_k, I0_k = mu_t[:, keep], I0[:, keep]
+    per = max(1, 200_000 // (geom.n_rows * geom.n_cols))
+    chunks = _views_chunks(geom.n_views, per)
+    out = np.empty((2, geom.n_rays))
+
+    def work(views):
+        S, P = G.ray_endpoints(geom, views)
+        A = lengths(S, P) @ mu_k               # (n, nE) line integrals per energy
+        g = np.exp(-A) @ I0_k.T                # (n, 2)
+        a = views[0] * geom.n_rows * geom.n_cols
+        out[:, a:a + g.shape[0]] = g.T
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, chunks))
+    return out
+
+
+def make_inputs(name: str, seed=None, i0=None, with_data=True):
+    geom = geometry_for(name)
+    i0_d, seed_d, n_iter = WORKLOADS[name]
+    seed = seed_d if seed is None else seed
+    i0 = i0_d if i0 is None else i0
+    I0 = spectra(i0)
+    mu = basis_mu()
+    inp = dict(name=name, geom=geom, I0=I0, mu=mu, energies=ENERGY_KEV.copy(),
+               n_iter=n_iter, seed=seed)
+    ph = phantom_for(name)
+    ss = 4 if geom.kind == G.FAN2D else 2
+    frac = metal_fraction(ph, geom, ss)
+    inp["metal"] = (frac >= 0.5).astype(np.uint8).reshape(-1)
+    inp["t"] = 0.5 * min(geom.dx, geom.dy)
+    inp["c0"] = cold_start(geom, I0)
+    inp["Z"] = surrogate_Z(geom, mu, I0)
+    if with_data:
+        gbar = expected_counts(geom, ph, I0)
+        rng = np.random.default_rng(seed)
+        inp["gbar"] = gbar
+        inp["d"] = rng.poisson(gbar).astype(np.float32)
+    return inp
+
+
+def cold_start(geom, I0):
+    """Water (in basis fractions) inside the disk inscribed in the grid, zero outside."""
+    w = water_in_basis(I0)
+    x, y = voxel_centres(geom)
+    r = 0.5 * min(geom.nx * geom.dx, geom.ny * geom.dy)
+    disk = (x[None, :] ** 2 + y[:, None] ** 2) <= r * r
+    nz = geom.nz if geom.kind == G.HELICAL3D else 1
+    disk = np.broadcast_to(disk, (nz,) + disk.shape).reshape(-1)
+    return np.stack([w[0] * disk, w[1] * disk]).astype(np.float64)
+
+
+def surrogate_Z(geom, mu, I0):
+    """Z_i = 2 * max_E mu_i(E) * (longest chord of the grid), over the energies
+    where some spectrum is non-zero; with this choice the weights
+    h(x,y) mu_i(E) / Z_i of any ray sum to at most one."""
+    keep = I0.sum(axis=0) > 0
+    return 2.0 * mu[:, keep].max(axis=1) * geom.box_diagonal()
+
+
+def blob_inputs(name="fan256", seed_c=4, seed_true=40, i0=1e5, n_blobs=20):
+    """Gradient workload: smooth positive basis images (Gaussian-blob sums).
+
+    Returns the evaluation point c (blobs sampled at voxel centres, seed_c) and
+    Poisson data of an independent blob phantom (seed_true), simulated from its
+    closed-form line integrals."""
+    geom = geometry_for(name)
+    I0 = spectra(i0)
+    mu = basis_mu()
+    ph_c = random_blobs(seed_c, n_blobs, 100.0 * geom.nx / 256, geom)
+    ph_t = random_blobs(seed_true, n_blobs, 100.0 * geom.nx / 256, geom)
+    x, y = voxel_centres(geom)
+    X = np.stack(np.meshgrid(x, y, indexing="xy"), axis=-1)
+    c = ph_c.sample(X).reshape(-1, 2).T.copy()
+    gbar = expected_counts(geom, ph_t, I0)
+    rng = np.random.default_rng(seed_true)
+    d = rng.poisson(gbar).astype(np.float32)
+    return dict(name=name, geom=geom, I0=I0, mu=mu, c=c, d=d, gbar=gbar,
+                Z=surrogate_Z(geom, mu, I0))
