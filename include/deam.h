@@ -172,6 +172,19 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
                  const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
                  void* stream);
 
+/* deam_iterate with per-kernel device timing, for benchmarks and profiling.
+ * Same arguments and results as deam_iterate, plus
+ *   kernel_ms  host [4] float output: summed device time (ms, HIP events
+ *              recorded on `stream`) over the n_iter iterations of
+ *              [0] the forward-projection + poly-mean kernel,
+ *              [1] the backprojection kernel,
+ *              [2] the update kernel,
+ *              [3] the whole loop (first to last event).
+ * Synchronises `stream` before returning. */
+int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                       const double* Z, int32_t n_iter, double* obj_hist, void* ws,
+                       size_t ws_bytes, void* stream, float* kernel_ms);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* deam_last_error(void);
 

@@ -1,0 +1,525 @@
+// C ABI of the gfx950 DEAM library: argument checks, plan tables, workspace
+// layout and the order of kernel launches.  No C++ exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "deam_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return DEAM_OK;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(DEAM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t real_size(const deam_plan* p) { return p->precision == DEAM_PREC_FP64 ? 8 : 4; }
+
+int check_plan(const deam_plan* p) {
+  if (!p) return fail(DEAM_ERR_NULL, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(DEAM_ERR_HIP, "hipGetDevice failed");
+  if (dev != p->device)
+    return fail(DEAM_ERR_VALUE, "current device %d differs from the plan's device %d", dev,
+                p->device);
+  return DEAM_OK;
+}
+
+// Tile of the backprojector for `bpv` bytes of accumulators per voxel:
+// tz = min(nz, 64) slices and as many columns as fit in 64 KiB of LDS
+// (capped at 16 x 16).
+deam::Tiling choose_tiling(const deam_geometry& g, int bpv) {
+  deam::Tiling t{};
+  const int nz = g.kind == DEAM_HELICAL3D ? g.nz : 1;
+  t.tz = std::min(nz, 64);
+  int cols = std::max(1, 65536 / (t.tz * bpv));
+  int tx = 1, ty = 1;
+  while (tx * ty * 2 <= cols && (tx < 16 || ty < 16)) {
+    if (tx <= ty && tx < 16) tx *= 2;
+    else if (ty < 16) ty *= 2;
+    else tx *= 2;
+  }
+  t.tx = tx;
+  t.ty = ty;
+  t.ntx = (g.nx + tx - 1) / tx;
+  t.nty = (g.ny + ty - 1) / ty;
+  t.ntz = (nz + t.tz - 1) / t.tz;
+  return t;
+}
+
+// Upper bound of max_x sum_y h(x,y): per view at most nk channels and nr rows
+// pass through one voxel, each with a chord no longer than the voxel diagonal.
+double h1_bound(const deam_geometry& g) {
+  const bool is3d = g.kind == DEAM_HELICAL3D;
+  const double rc = 0.5 * std::hypot(g.nx * g.dx, g.ny * g.dy);
+  const double dmin = g.sid - rc;
+  const double rho = 0.5 * std::hypot(g.dx, g.dy);
+  const double w = 2.0 * std::asin(std::min(1.0, rho / dmin));
+  const double nk = std::floor(w / g.dgamma) + 2.0;
+  double nr = 1.0, diag = std::hypot(g.dx, g.dy);
+  if (is3d) {
+    const double dzeta = g.drow_iso * g.sdd / g.sid;
+    const double zmax = 0.5 * (g.n_rows - 1) * dzeta;
+    const double width = (g.dz * g.sdd + 2.0 * rho * zmax) / dmin;
+    nr = std::min<double>(std::floor(width / dzeta) + 2.0, g.n_rows);
+    diag = std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz);
+  }
+  return (double)g.n_views * std::min<double>(nk, g.n_cols) * nr * diag;
+}
+
+int validate_geometry(const deam_geometry* g) {
+  if (!g) return fail(DEAM_ERR_NULL, "geometry is NULL");
+  if (g->kind != DEAM_FAN2D && g->kind != DEAM_HELICAL3D)
+    return fail(DEAM_ERR_GEOMETRY, "unknown geometry kind %d", g->kind);
+  const bool is3d = g->kind == DEAM_HELICAL3D;
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_views <= 0 || g->n_rows <= 0 ||
+      g->n_cols <= 0)
+    return fail(DEAM_ERR_SHAPE, "grid and detector sizes must be positive");
+  if (!is3d && (g->nz != 1 || g->n_rows != 1))
+    return fail(DEAM_ERR_SHAPE, "a fan-beam geometry needs nz = 1 and n_rows = 1");
+  const double V = (double)g->nx * g->ny * g->nz;
+  const double R = (double)g->n_views * g->n_rows * g->n_cols;
+  if (V >= 2147483647.0 || R >= 2147483647.0)
+    return fail(DEAM_ERR_SHAPE, "more than 2^31 voxels or rays");
+  if (!(g->dx > 0 && g->dy > 0 && g->dz > 0 && std::isfinite(g->dx * g->dy * g->dz)))
+    return fail(DEAM_ERR_GEOMETRY, "voxel sizes must be positive and finite");
+  if (!(g->dgamma > 0 && std::isfinite(g->dgamma)))
+    return fail(DEAM_ERR_GEOMETRY, "dgamma must be positive");
+  if (!(g->views_per_rot > 0 && std::isfinite(g->views_per_rot)))
+    return fail(DEAM_ERR_GEOMETRY, "views_per_rot must be positive");
+  if (!(std::isfinite(g->beta0) && std::isfinite(g->col_offset) && std::isfinite(g->feed_per_rot)))
+    return fail(DEAM_ERR_GEOMETRY, "non-finite geometry parameter");
+  if (is3d && !(g->drow_iso > 0 && std::isfinite(g->drow_iso)))
+    return fail(DEAM_ERR_GEOMETRY, "drow_iso must be positive");
+  const double rc = 0.5 * std::hypot(g->nx * g->dx, g->ny * g->dy);
+  if (!(g->sid > rc))
+    return fail(DEAM_ERR_GEOMETRY, "the source circle (sid=%g) must lie outside the grid (radius %g)",
+                g->sid, rc);
+  if (!(g->sdd > g->sid + rc))
+    return fail(DEAM_ERR_GEOMETRY, "the detector must lie beyond the grid (sdd > sid + grid radius)");
+  const double half_fan = 0.5 * g->n_cols * g->dgamma + std::fabs(g->col_offset) * g->dgamma;
+  if (!(half_fan < 1.5))
+    return fail(DEAM_ERR_GEOMETRY, "the fan must be narrower than about 170 degrees");
+  return DEAM_OK;
+}
+
+template <typename T>
+void fill_energy(std::vector<unsigned char>& out, int& nE, int n_energy, const double* I0,
+                 const double* mu) {
+  std::vector<deam::EBin<T>> bins;
+  for (int e = 0; e < n_energy; ++e) {
+    const double il = I0[e], ih = I0[n_energy + e];
+    if (il == 0.0 && ih == 0.0) continue;
+    const double m1 = mu[e], m2 = mu[n_energy + e];
+    deam::EBin<T> b;
+    b.mu1 = (T)m1;
+    b.mu2 = (T)m2;
+    b.i0l = (T)il;
+    b.i0h = (T)ih;
+    b.m1l = (T)(m1 * il);
+    b.m2l = (T)(m2 * il);
+    b.m1h = (T)(m1 * ih);
+    b.m2h = (T)(m2 * ih);
+    bins.push_back(b);
+  }
+  while (bins.size() % 8 != 0 || bins.empty()) bins.push_back(deam::EBin<T>{});  // zero records
+  nE = (int)bins.size();
+  out.resize(bins.size() * sizeof(deam::EBin<T>));
+  std::memcpy(out.data(), bins.data(), out.size());
+}
+
+}  // namespace
+
+namespace deam {
+
+WsLayout workspace_layout(const deam_plan* p, int op) {
+  WsLayout L{};
+  const size_t rs = p->precision == DEAM_PREC_FP64 ? 8 : 4;
+  const size_t V = (size_t)p->gd.V, R = (size_t)p->gd.R;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t nblk = (size_t)p->fp_blocks;
+  switch (op) {
+    case DEAM_OP_FORWARD:
+      L.cp_y = take(V * 2 * rs);
+      L.cp_x = take(V * 2 * rs);
+      break;
+    case DEAM_OP_METAL_TRACE:
+      L.cp_y = take(V * 2 * 8);
+      L.cp_x = take(V * 2 * 8);
+      break;
+    case DEAM_OP_POLY_MEAN:
+      L.partial = take(nblk * 8);
+      L.wmax = take(64);
+      L.scratch = take(64);
+      break;
+    case DEAM_OP_BACKPROJECT:
+      L.wmax = take(64);
+      break;
+    case DEAM_OP_ITERATE:
+    default:
+      L.cp_y = take(V * 2 * rs);
+      L.cp_x = take(V * 2 * rs);
+      L.w = take(R * 4 * rs);
+      L.b = take(V * 4 * rs);
+      L.partial = take(nblk * 8);
+      L.wmax = take(64);
+      L.scratch = take(64);
+      break;
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace deam
+
+extern "C" {
+
+const char* deam_last_error(void) { return g_err.c_str(); }
+
+int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* I0,
+                     const double* mu, int32_t precision, deam_plan** out) {
+  if (!out) return fail(DEAM_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (int rc = validate_geometry(geom)) return rc;
+  if (!I0 || !mu) return fail(DEAM_ERR_NULL, "I0 or mu is NULL");
+  if (n_energy <= 0 || n_energy > 100000) return fail(DEAM_ERR_SHAPE, "n_energy out of range");
+  if (precision != DEAM_PREC_MIXED && precision != DEAM_PREC_FP64)
+    return fail(DEAM_ERR_VALUE, "unknown precision %d", precision);
+  for (int i = 0; i < 2 * n_energy; ++i) {
+    if (!(std::isfinite(I0[i]) && I0[i] >= 0.0))
+      return fail(DEAM_ERR_VALUE, "I0 must be finite and non-negative");
+    if (!(std::isfinite(mu[i]) && mu[i] >= 0.0))
+      return fail(DEAM_ERR_VALUE, "mu must be finite and non-negative");
+  }
+  const deam_geometry& g = *geom;
+  const bool is3d = g.kind == DEAM_HELICAL3D;
+
+  deam_plan* p = new (std::nothrow) deam_plan();
+  if (!p) return fail(DEAM_ERR_VALUE, "out of host memory");
+  p->g = g;
+  p->precision = precision;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(DEAM_ERR_HIP, "hipGetDevice failed");
+  }
+
+  // geometry tables (FP64)
+  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_cols * 2 + (size_t)g.n_rows);
+  double* tv = tab.data();
+  double* tc = tv + (size_t)g.n_views * 4;
+  double* tz = tc + (size_t)g.n_cols * 2;
+  for (int v = 0; v < g.n_views; ++v) {
+    const double beta = g.beta0 + 2.0 * M_PI * (double)v / g.views_per_rot;
+    tv[4 * v] = std::cos(beta);
+    tv[4 * v + 1] = std::sin(beta);
+    tv[4 * v + 2] = is3d ? ((double)v - 0.5 * (g.n_views - 1)) * g.feed_per_rot / g.views_per_rot : 0.0;
+    tv[4 * v + 3] = 0.0;
+  }
+  for (int k = 0; k < g.n_cols; ++k) {
+    const double gam = ((double)k - 0.5 * (g.n_cols - 1) - g.col_offset) * g.dgamma;
+    tc[2 * k] = std::cos(gam);
+    tc[2 * k + 1] = std::sin(gam);
+  }
+  const double dzeta = is3d ? g.drow_iso * g.sdd / g.sid : 1.0;
+  for (int r = 0; r < g.n_rows; ++r) tz[r] = is3d ? ((double)r - 0.5 * (g.n_rows - 1)) * dzeta : 0.0;
+
+  std::vector<unsigned char> etab;
+  if (precision == DEAM_PREC_FP64) fill_energy<double>(etab, p->nE, n_energy, I0, mu);
+  else fill_energy<float>(etab, p->nE, n_energy, I0, mu);
+
+  if (hipMalloc(&p->d_tables, tab.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_energy, etab.size()) != hipSuccess) {
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    delete p;
+    return fail(DEAM_ERR_HIP, "hipMalloc of plan tables failed");
+  }
+  if (hipMemcpy(p->d_tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->d_energy, etab.data(), etab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->d_tables);
+    (void)hipFree(p->d_energy);
+    delete p;
+    return fail(DEAM_ERR_HIP, "hipMemcpy of plan tables failed");
+  }
+
+  deam::GeomDev& G = p->gd;
+  G.is3d = is3d ? 1 : 0;
+  G.nx = g.nx;
+  G.ny = g.ny;
+  G.nz = is3d ? g.nz : 1;
+  G.n_views = g.n_views;
+  G.n_rows = g.n_rows;
+  G.n_cols = g.n_cols;
+  G.dx = g.dx;
+  G.dy = g.dy;
+  G.dz = g.dz;
+  G.inv_dx = 1.0 / g.dx;
+  G.inv_dy = 1.0 / g.dy;
+  G.inv_dz = 1.0 / g.dz;
+  G.x0 = -0.5 * g.nx * g.dx;
+  G.y0 = -0.5 * g.ny * g.dy;
+  G.z0 = -0.5 * G.nz * g.dz;
+  G.sid = g.sid;
+  G.sdd = g.sdd;
+  G.dgamma = g.dgamma;
+  G.kc = 0.5 * (g.n_cols - 1) + g.col_offset;
+  G.dzeta = dzeta;
+  G.rc = 0.5 * (g.n_rows - 1);
+  G.view = (const double*)p->d_tables;
+  G.chan = G.view + (size_t)g.n_views * 4;
+  G.zeta = G.chan + (size_t)g.n_cols * 2;
+  G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
+  G.V = (int64_t)g.nx * g.ny * G.nz;
+
+  p->h1_bound = h1_bound(g);
+  p->tile_packed = choose_tiling(g, 16);
+  const int rs8 = 8;
+  p->tile_i64[1] = choose_tiling(g, 1 * rs8);
+  p->tile_i64[2] = choose_tiling(g, 2 * rs8);
+  p->tile_i64[3] = choose_tiling(g, 3 * rs8);
+  p->tile_i64[4] = choose_tiling(g, 4 * rs8);
+  p->fp_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
+  *out = p;
+  return ok();
+}
+
+int deam_plan_destroy(deam_plan* plan) {
+  if (!plan) return fail(DEAM_ERR_NULL, "plan is NULL");
+  (void)hipFree(plan->d_tables);
+  (void)hipFree(plan->d_energy);
+  delete plan;
+  return ok();
+}
+
+int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels) {
+  if (!plan || !n_rays || !n_voxels) return fail(DEAM_ERR_NULL, "NULL argument");
+  *n_rays = plan->gd.R;
+  *n_voxels = plan->gd.V;
+  return ok();
+}
+
+int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes) {
+  if (!plan || !bytes) return fail(DEAM_ERR_NULL, "NULL argument");
+  if (op < DEAM_OP_FORWARD || op > DEAM_OP_METAL_TRACE)
+    return fail(DEAM_ERR_VALUE, "unknown op %d", op);
+  *bytes = deam::workspace_layout(plan, op).total;
+  return ok();
+}
+
+static int check_ws(const deam_plan* p, int op, const void* ws, size_t ws_bytes,
+                    deam::WsLayout& L) {
+  L = deam::workspace_layout(p, op);
+  if (L.total > 0 && !ws) return fail(DEAM_ERR_NULL, "workspace is NULL");
+  if (ws_bytes < L.total)
+    return fail(DEAM_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(DEAM_ERR_VALUE, "workspace must be 256-byte aligned");
+  return DEAM_OK;
+}
+
+int deam_metal_trace(const deam_plan* plan, const uint8_t* M, double t, uint8_t* mask, double* T,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!M || !mask) return fail(DEAM_ERR_NULL, "M or mask is NULL");
+  if (!std::isfinite(t)) return fail(DEAM_ERR_VALUE, "threshold must be finite");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_METAL_TRACE, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(deam::launch_pack(plan, M, 1, true, true, w + L.cp_y, w + L.cp_x, st));
+  HIP_TRY(deam::launch_metal_trace(plan, w + L.cp_y, w + L.cp_x, t, mask, T, st));
+  return ok();
+}
+
+int deam_forward(const deam_plan* plan, const void* c, int32_t n_ch, void* l, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c || !l) return fail(DEAM_ERR_NULL, "c or l is NULL");
+  if (n_ch != 1 && n_ch != 2) return fail(DEAM_ERR_SHAPE, "n_ch must be 1 or 2 (got %d)", n_ch);
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_FORWARD, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  const bool dbl = plan->precision == DEAM_PREC_FP64;
+  HIP_TRY(deam::launch_pack(plan, c, n_ch, false, dbl, w + L.cp_y, w + L.cp_x, st));
+  HIP_TRY(deam::launch_forward(plan, w + L.cp_y, w + L.cp_x, l, n_ch, st));
+  return ok();
+}
+
+int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const uint8_t* mask,
+                   int32_t mode, const void* v, void* w, void* g, double* obj, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!l || !w) return fail(DEAM_ERR_NULL, "l or w is NULL");
+  if (mode != DEAM_W_AM && mode != DEAM_W_GRAD && mode != DEAM_W_VJP)
+    return fail(DEAM_ERR_VALUE, "unknown weight mode %d", mode);
+  if (mode == DEAM_W_VJP && !v) return fail(DEAM_ERR_NULL, "v is NULL in VJP mode");
+  if (mode != DEAM_W_VJP && !d) return fail(DEAM_ERR_NULL, "d is NULL");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_POLY_MEAN, ws, ws_bytes, L)) return rc;
+  char* wsb = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  const int pm = mode == DEAM_W_AM ? deam::PM_AM : (mode == DEAM_W_GRAD ? deam::PM_GRAD : deam::PM_VJP);
+  uint32_t* wmax = (uint32_t*)(wsb + L.wmax);
+  double* partial = (double*)(wsb + L.partial);
+  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
+  if (obj) {
+    const int64_t nb = (plan->gd.R + deam::kFpBlock - 1) / deam::kFpBlock;
+    HIP_TRY(deam::launch_reduce(partial, nb, obj, st));
+  }
+  return ok();
+}
+
+int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!w || !b) return fail(DEAM_ERR_NULL, "w or b is NULL");
+  if (n_ch != 1 && n_ch != 2 && n_ch != 4)
+    return fail(DEAM_ERR_SHAPE, "n_ch must be 1, 2 or 4 (got %d)", n_ch);
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_BACKPROJECT, ws, ws_bytes, L)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* wmax = (uint32_t*)((char*)ws + L.wmax);
+  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_absmax(plan, w, n_ch, wmax, st));
+  HIP_TRY(deam::launch_backproject(plan, w, n_ch, deam::ACC_I64, wmax, b, st));
+  return ok();
+}
+
+int deam_update(const deam_plan* plan, double* c64, void* c_proj, const void* b, const double* Z,
+                void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c64 || !b || !Z) return fail(DEAM_ERR_NULL, "c64, b or Z is NULL");
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  HIP_TRY(deam::launch_update(plan, c64, b, Z[0], Z[1], c_proj, nullptr, nullptr,
+                              (hipStream_t)stream));
+  return ok();
+}
+
+static int iterate_impl(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                        const double* Z, int32_t n_iter, double* obj_hist, void* ws,
+                        size_t ws_bytes, void* stream, float* kernel_ms) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c64 || !d || !Z) return fail(DEAM_ERR_NULL, "c64, d or Z is NULL");
+  if (n_iter < 0) return fail(DEAM_ERR_VALUE, "n_iter must be >= 0");
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_ITERATE, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  void* cpy = w + L.cp_y;
+  void* cpx = w + L.cp_x;
+  uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  double* partial = (double*)(w + L.partial);
+  const int acc = plan->precision == DEAM_PREC_FP64 ? deam::ACC_I64 : deam::ACC_PACKED;
+  // events: per iteration, before/after the ray kernel, before/after the
+  // backprojection, after the update
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  };
+  if (kernel_ms) {
+    ev.resize((size_t)5 * std::max(n_iter, 1), nullptr);
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        cleanup();
+        return fail(DEAM_ERR_HIP, "hipEventCreate failed");
+      }
+  }
+  auto mark = [&](int k, int j) -> hipError_t {
+    return kernel_ms ? hipEventRecord(ev[(size_t)5 * k + j], st) : hipSuccess;
+  };
+#define STEP(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      cleanup();                                                                           \
+      return fail(DEAM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));                   \
+    }                                                                                      \
+  } while (0)
+  // projection copies of the starting image
+  STEP(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
+  for (int k = 0; k < n_iter; ++k) {
+    STEP(deam::launch_fill_u32(wmax, 0u, 16, st));
+    STEP(mark(k, 0));
+    STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
+    STEP(mark(k, 1));
+    if (obj_hist) STEP(deam::launch_reduce(partial, plan->fp_blocks, obj_hist + k, st));
+    STEP(mark(k, 2));
+    STEP(deam::launch_backproject(plan, w + L.w, 4, acc, wmax, w + L.b, st));
+    STEP(mark(k, 3));
+    STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
+    STEP(mark(k, 4));
+  }
+  if (kernel_ms) {
+    STEP(hipStreamSynchronize(st));
+    float acc_ms[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < n_iter; ++k) {
+      float a = 0.f, b = 0.f, c = 0.f;
+      STEP(hipEventElapsedTime(&a, ev[(size_t)5 * k], ev[(size_t)5 * k + 1]));
+      STEP(hipEventElapsedTime(&b, ev[(size_t)5 * k + 2], ev[(size_t)5 * k + 3]));
+      STEP(hipEventElapsedTime(&c, ev[(size_t)5 * k + 3], ev[(size_t)5 * k + 4]));
+      acc_ms[0] += a;
+      acc_ms[1] += b;
+      acc_ms[2] += c;
+    }
+    kernel_ms[0] = acc_ms[0];
+    kernel_ms[1] = acc_ms[1];
+    kernel_ms[2] = acc_ms[2];
+    kernel_ms[3] = 0.f;
+    if (n_iter > 0)
+      STEP(hipEventElapsedTime(&kernel_ms[3], ev[0], ev[(size_t)5 * (n_iter - 1) + 4]));
+  }
+#undef STEP
+  cleanup();
+  return ok();
+}
+
+int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                 const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
+                 void* stream) {
+  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
+}
+
+int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                       const double* Z, int32_t n_iter, double* obj_hist, void* ws,
+                       size_t ws_bytes, void* stream, float* kernel_ms) {
+  if (!kernel_ms) return fail(DEAM_ERR_NULL, "kernel_ms is NULL");
+  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, kernel_ms);
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal declarations of the gfx950 DEAM library (plan layout, kernel
+// parameter blocks, launchers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/deam.h"
+
+namespace deam {
+
+// Geometry as the kernels see it: scalars by value, per-view / per-channel /
+// per-row tables in device memory (FP64; the ray set-up is always FP64).
+struct GeomDev {
+  int is3d;
+  int nx, ny, nz;
+  int n_views, n_rows, n_cols;
+  double dx, dy, dz, inv_dx, inv_dy, inv_dz;
+  double x0, y0, z0;            // grid corner (mm)
+  double sid, sdd, dgamma, kc;  // kc = (n_cols-1)/2 + col_offset
+  double dzeta, rc;             // row pitch at the detector (mm), (n_rows-1)/2
+  const double* view;           // [n_views][4]: cos b, sin b, z_s, unused
+  const double* chan;           // [n_cols][2]:  cos g, sin g
+  const double* zeta;           // [n_rows]
+  int64_t R, V;
+};
+
+// Energy table, one record per kept bin (both spectra zero -> dropped).
+template <typename T>
+struct EBin {
+  T mu1, mu2;      // basis attenuation (1/mm)
+  T i0l, i0h;      // photons per ray, low / high spectrum
+  T m1l, m2l;      // mu1*i0l, mu2*i0l
+  T m1h, m2h;      // mu1*i0h, mu2*i0h
+};
+
+// Back-projection tile: tx*ty columns x tz slices owned by one workgroup.
+struct Tiling {
+  int tx, ty, tz;
+  int ntx, nty, ntz;
+};
+
+enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
+enum AccMode { ACC_PACKED = 0, ACC_I64 = 1 };
+
+constexpr int kFpBlock = 256;
+constexpr int kBpBlock = 256;
+constexpr int kViewBatch = 16;
+
+// Workspace pieces (byte offsets, 256-aligned).
+struct WsLayout {
+  size_t cp_y, cp_x;     // packed projection images (natural and transposed)
+  size_t w;              // per-ray weights
+  size_t b;              // back-projections
+  size_t partial;        // per-block FP64 partial sums
+  size_t wmax;           // per-channel max |w| (uint32 float bits)
+  size_t scratch;        // small FP64 scratch
+  size_t total;
+};
+
+}  // namespace deam
+
+struct deam_plan {
+  deam_geometry g;
+  int precision;
+  int device;
+  deam::GeomDev gd;
+  int nE;                        // kept energy bins
+  void* d_tables;                // view/chan/zeta tables (FP64)
+  void* d_energy;                // EBin<float> or EBin<double> [nE]
+  double h1_bound;               // upper bound of max_x sum_y h(x,y)
+  deam::Tiling tile_packed;      // BP tiling for 2 packed u64 per voxel
+  deam::Tiling tile_i64[5];      // BP tiling for n_ch int64 per voxel (index n_ch)
+  int64_t fp_blocks;             // blocks of the ray kernels
+};
+
+namespace deam {
+
+// Launchers (deam_kernels.hip).  All asynchronous on `st`.
+hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8, bool dbl,
+                       void* cp_y, void* cp_x, hipStream_t st);
+hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
+                          int n_out, hipStream_t st);
+hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* cp_x, double t,
+                              uint8_t* mask, double* T, hipStream_t st);
+hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
+                          const uint8_t* mask, int mode, void* w, double* partial,
+                          uint32_t* wmax, hipStream_t st);
+hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
+                       int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
+                       hipStream_t st);
+hipError_t launch_reduce(const double* partial, int64_t n, double* out, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmax, hipStream_t st);
+hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, int acc,
+                              const uint32_t* wmax, void* b, hipStream_t st);
+hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
+                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st);
+
+WsLayout workspace_layout(const deam_plan* p, int op);
+
+}  // namespace deam

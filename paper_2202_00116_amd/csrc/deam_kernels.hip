@@ -1,0 +1,851 @@
+// gfx950 kernels of the DEAM hot path (Ge et al., Section 2.3, Eqs. 5-11).
+//
+// Projector.  h(x,y) is the exact intersection length of ray y with voxel x
+// (the system operator of Eq. 8).  Rays are walked along their driving axis
+// (the in-plane axis along which the ray advances fastest, so the lateral
+// and axial slopes are at most 1 in grid units): each step crosses one grid
+// plane of that axis, and inside the step the ray is split at the lateral
+// (and, in 3D, axial) plane it crosses.  This yields exactly the segments of
+// Siddon's method, grouped per plane step, so that the 64 lanes of a
+// wavefront (64 neighbouring channels of one view) move through the same
+// image row at the same time and read neighbouring pixels.  Rays driven
+// along x read a transposed copy of the image so those reads stay
+// contiguous too.
+//
+// Backprojection.  Floating-point atomics are slow on this part (both in LDS
+// and in L2), while LDS integer atomics run at full rate.  Each workgroup
+// owns a tile of voxels in LDS, loops over all views, walks every ray that
+// crosses its tile (clipped to the tile) and accumulates h*w in fixed point
+// with 64-bit integer LDS atomics.  Integer addition is associative, so the
+// result is bitwise reproducible, and the tile is written once with plain
+// stores: no global atomics, no partial images.
+#include "deam_internal.hpp"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+namespace deam {
+namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+
+// Logical block index that gives each XCD a contiguous range of blocks
+// (blocks are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------------------
+// Ray set-up (FP64) and the plane-by-plane walk (plan precision)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Ray {
+  T b0, mb;       // lateral grid coordinate b(a) = b0 + a*mb
+  T w0, mw, imw;  // axial grid coordinate w(a) = w0 + a*mw, imw = 1/|mw|
+  T La, Lb;       // mm of ray per unit of a, per unit of b
+  T alo, ahi;     // range of a inside the clip box
+  int ydrive;     // 1: a = y (rows) and b = x; 0: a = x and b = y
+};
+
+// Ray (v, r, k) clipped to the box [lo, hi] (grid units, axes x, y, z).
+template <typename T>
+__device__ bool ray_setup(const GeomDev& G, int v, int r, int k, double lox, double loy,
+                          double loz, double hix, double hiy, double hiz, Ray<T>& ry) {
+  const double cb = G.view[4 * v], sb = G.view[4 * v + 1], zs = G.view[4 * v + 2];
+  const double cg = G.chan[2 * k], sg = G.chan[2 * k + 1];
+  const double ex = -(cg * cb - sg * sb), ey = -(sg * cb + cg * sb);  // R(gamma) u
+  const double Dz = G.is3d ? G.zeta[r] : 0.0;
+  const double su = (G.sid * cb - G.x0) * G.inv_dx;
+  const double sv = (G.sid * sb - G.y0) * G.inv_dy;
+  const double sw = (zs - G.z0) * G.inv_dz;
+  const double du = G.sdd * ex * G.inv_dx, dv = G.sdd * ey * G.inv_dy, dw = Dz * G.inv_dz;
+  const double L = sqrt(G.sdd * G.sdd + Dz * Dz);
+  const bool yd = fabs(dv) >= fabs(du);
+  const double sa = yd ? sv : su, da = yd ? dv : du;
+  const double sbb = yd ? su : sv, db = yd ? du : dv;
+  const double alo_box = yd ? loy : lox, ahi_box = yd ? hiy : hix;
+  const double blo_box = yd ? lox : loy, bhi_box = yd ? hix : hiy;
+  const double mb = db / da, mw = dw / da;
+  const double b0 = sbb - sa * mb, w0 = sw - sa * mw;
+  double alo = fmax(fmin(sa, sa + da), alo_box);
+  double ahi = fmin(fmax(sa, sa + da), ahi_box);
+  if (mb != 0.0) {
+    const double t0 = (blo_box - b0) / mb, t1 = (bhi_box - b0) / mb;
+    alo = fmax(alo, fmin(t0, t1));
+    ahi = fmin(ahi, fmax(t0, t1));
+  } else if (!(b0 >= blo_box && b0 < bhi_box)) {
+    return false;
+  }
+  if (G.is3d) {
+    if (mw != 0.0) {
+      const double t0 = (loz - w0) / mw, t1 = (hiz - w0) / mw;
+      alo = fmax(alo, fmin(t0, t1));
+      ahi = fmin(ahi, fmax(t0, t1));
+    } else if (!(w0 >= loz && w0 < hiz)) {
+      return false;
+    }
+  }
+  if (!(ahi > alo)) return false;
+  ry.b0 = (T)b0;
+  ry.mb = (T)mb;
+  ry.w0 = (T)w0;
+  ry.mw = (T)mw;
+  ry.imw = mw != 0.0 ? (T)(1.0 / fabs(mw)) : (T)0;
+  ry.La = (T)(L / fabs(da));
+  ry.Lb = db != 0.0 ? (T)(L / fabs(db)) : (T)FLT_MAX;
+  ry.alo = (T)alo;
+  ry.ahi = (T)ahi;
+  ry.ydrive = yd ? 1 : 0;
+  return true;
+}
+
+// One piece [va, vb] of a plane step at axial index iw: split at the
+// lateral plane it crosses (at most one, since |mb| <= 1).
+template <typename T, typename F>
+__device__ __forceinline__ void walk_piece(const Ray<T>& ry, int ia, T va, T vb, int iw, int blo,
+                                           int bhi, F& visit) {
+  const T ba = fma(va, ry.mb, ry.b0), bb = fma(vb, ry.mb, ry.b0);
+  const int A = clampi((int)floor(ba), blo, bhi - 1);
+  int B = clampi((int)floor(bb), blo, bhi - 1);
+  B = clampi(B, A - 1, A + 1);
+  const T seg = (vb - va) * ry.La;
+  T hA = seg;
+  if (A != B) hA = fmin(fabs((T)(A > B ? A : B) - ba) * ry.Lb, seg);
+  visit(ia, A, iw, hA);
+  visit(ia, B, iw, seg - hA);
+}
+
+// Walk the plane steps ia of the driving axis inside [alo, ahi], restricted
+// to lateral indices [blo, bhi) and axial indices [wlo, whi).  visit(ia, ib,
+// iw, h) receives every segment (h may be 0); flush() is called every 16
+// steps (used for compensated summation).
+template <typename T, bool Z3, typename F, typename G>
+__device__ __forceinline__ void walk(const Ray<T>& ry, int alo_i, int ahi_i, int blo, int bhi,
+                                     int wlo, int whi, F& visit, G& flush) {
+  const int ia0 = max((int)floor(ry.alo), alo_i);
+  const int ia1 = min((int)ceil(ry.ahi) - 1, ahi_i - 1);
+  int cnt = 0;
+  for (int ia = ia0; ia <= ia1; ++ia) {
+    const T va = fmax((T)ia, ry.alo), vb = fmin((T)(ia + 1), ry.ahi);
+    if (vb > va) {
+      if constexpr (Z3) {
+        const T wa = fma(va, ry.mw, ry.w0), wb = fma(vb, ry.mw, ry.w0);
+        int C = clampi((int)floor(wa), wlo, whi - 1);
+        const int D = clampi((int)floor(wb), wlo, whi - 1);
+        T vcur = va, wcur = wa;
+        while (C != D) {  // axial plane crossings inside this step (rare)
+          const int dir = D > C ? 1 : -1;
+          const T wz = (T)(dir > 0 ? C + 1 : C);
+          const T vz = fmin(fmax(vcur + fabs(wz - wcur) * ry.imw, vcur), vb);
+          walk_piece(ry, ia, vcur, vz, C, blo, bhi, visit);
+          vcur = vz;
+          wcur = wz;
+          C += dir;
+        }
+        walk_piece(ry, ia, vcur, vb, C, blo, bhi, visit);
+      } else {
+        walk_piece(ry, ia, va, vb, 0, blo, bhi, visit);
+      }
+    }
+    if (++cnt == 16) {
+      flush();
+      cnt = 0;
+    }
+  }
+  flush();
+}
+
+template <typename T>
+__device__ __forceinline__ void neumaier(T& s, T& c, T x) {
+  const T t = s + x;
+  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// Line integrals of the two packed components along one ray (compensated).
+template <typename T, bool Z3>
+__device__ void project_ray(const GeomDev& G, const typename Vec2<T>::type* __restrict__ cpy,
+                            const typename Vec2<T>::type* __restrict__ cpx, int v, int r, int k,
+                            T& l1, T& l2) {
+  l1 = 0;
+  l2 = 0;
+  Ray<T> ry;
+  if (!ray_setup<T>(G, v, r, k, 0.0, 0.0, 0.0, (double)G.nx, (double)G.ny,
+                    (double)(G.is3d ? G.nz : 1), ry))
+    return;
+  const typename Vec2<T>::type* __restrict__ base = ry.ydrive ? cpy : cpx;
+  const uint32_t nb = ry.ydrive ? G.nx : G.ny;
+  const uint32_t na = ry.ydrive ? G.ny : G.nx;
+  const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
+  T s1 = 0, c1 = 0, s2 = 0, c2 = 0, p1 = 0, p2 = 0;
+  auto visit = [&](int ia, int ib, int iw, T h) {
+    const auto cv = base[(uint32_t)iw * plane + (uint32_t)ia * nb + (uint32_t)ib];
+    p1 = fma(h, cv.x, p1);
+    p2 = fma(h, cv.y, p2);
+  };
+  auto flush = [&]() {
+    neumaier(s1, c1, p1);
+    neumaier(s2, c2, p2);
+    p1 = 0;
+    p2 = 0;
+  };
+  walk<T, Z3>(ry, 0, (int)na, 0, (int)nb, 0, G.is3d ? G.nz : 1, visit, flush);
+  l1 = s1 + c1;
+  l2 = s2 + c2;
+}
+
+// ---------------------------------------------------------------------------
+// Per-ray polyenergetic mean and weights
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void energy_sums(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, T g[2],
+                            T a[2][2]) {
+  T S[6] = {0, 0, 0, 0, 0, 0}, C[6] = {0, 0, 0, 0, 0, 0};
+  for (int e0 = 0; e0 < nE; e0 += 8) {  // nE is padded to a multiple of 8
+    T p[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const EBin<T> B = eb[e0 + e];
+      const T ex = dexp(-fma(B.mu1, l1, B.mu2 * l2));
+      p[0] = fma(B.i0l, ex, p[0]);
+      p[1] = fma(B.i0h, ex, p[1]);
+      p[2] = fma(B.m1l, ex, p[2]);
+      p[3] = fma(B.m2l, ex, p[3]);
+      p[4] = fma(B.m1h, ex, p[4]);
+      p[5] = fma(B.m2h, ex, p[5]);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) neumaier(S[i], C[i], p[i]);
+  }
+  g[0] = S[0] + C[0];
+  g[1] = S[1] + C[1];
+  a[0][0] = S[2] + C[2];  // sum_E mu1 q_L
+  a[1][0] = S[3] + C[3];  // sum_E mu2 q_L
+  a[0][1] = S[4] + C[4];  // sum_E mu1 q_H
+  a[1][1] = S[5] + C[5];  // sum_E mu2 q_H
+}
+
+// I-divergence term d ln(d/g) - d + g, written as g((1+rho) ln(1+rho) - rho)
+// with rho = (d - g)/g so that it does not cancel when d is close to g.
+__device__ __forceinline__ double idiv_term(double d, double g) {
+  if (!(g > 0.0)) return 0.0;
+  if (d <= 0.0) return g;
+  const double rho = (d - g) / g;
+  return g * ((1.0 + rho) * log1p(rho) - rho);
+}
+
+__device__ __forceinline__ double nll_term(double d, double g) {
+  if (!(g > 0.0)) return 0.0;
+  return d > 0.0 ? g - d * log(g) : g;
+}
+
+// Weights and objective term of one ray.  Returns |w| per channel in wabs.
+template <typename T, int MODE>
+__device__ void poly_epilogue(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, int64_t ray,
+                              int64_t R, const float* __restrict__ d,
+                              const uint8_t* __restrict__ mask, const T* __restrict__ v,
+                              T* __restrict__ w, T* __restrict__ gout, double& term, T wabs[4]) {
+  T g[2], a[2][2];
+  energy_sums<T>(eb, nE, l1, l2, g, a);
+  const bool metal = mask != nullptr && mask[ray] != 0;
+  if (gout) {
+    gout[ray] = g[0];
+    gout[R + ray] = g[1];
+  }
+  if constexpr (MODE == PM_VJP) {
+    const T vl = v[ray], vh = v[R + ray];
+    const T u1 = -(vl * a[0][0] + vh * a[0][1]);
+    const T u2 = -(vl * a[1][0] + vh * a[1][1]);
+    w[ray] = u1;
+    w[R + ray] = u2;
+    wabs[0] = fabs(u1);
+    wabs[1] = fabs(u2);
+    term = 0.0;
+    return;
+  } else {
+    const float dl = d[ray], dh = d[R + ray];
+    // r_j = d_j / g_j off the trace, 1 on it (p = q); r_j a_ij := 0 when g_j = 0
+    T rl = 1, rh = 1;
+    if (!metal) {
+      rl = g[0] > (T)0 ? (T)dl / g[0] : (T)0;
+      rh = g[1] > (T)0 ? (T)dh / g[1] : (T)0;
+    }
+    if constexpr (MODE == PM_AM) {
+      const T wt1 = fma(rl, a[0][0], rh * a[0][1]);
+      const T wt2 = fma(rl, a[1][0], rh * a[1][1]);
+      const T wh1 = a[0][0] + a[0][1];
+      const T wh2 = a[1][0] + a[1][1];
+      w[ray] = metal ? wh1 : wt1;
+      w[R + ray] = metal ? wh2 : wt2;
+      w[2 * R + ray] = wh1;
+      w[3 * R + ray] = wh2;
+      wabs[0] = metal ? wh1 : wt1;
+      wabs[1] = metal ? wh2 : wt2;
+      wabs[2] = wh1;
+      wabs[3] = wh2;
+      term = metal ? 0.0 : idiv_term(dl, (double)g[0]) + idiv_term(dh, (double)g[1]);
+    } else {  // PM_GRAD: u_i = sum_j (r_j - 1) a_ij
+      const T u1 = metal ? (T)0 : fma(rl - 1, a[0][0], (rh - 1) * a[0][1]);
+      const T u2 = metal ? (T)0 : fma(rl - 1, a[1][0], (rh - 1) * a[1][1]);
+      w[ray] = u1;
+      w[R + ray] = u2;
+      wabs[0] = fabs(u1);
+      wabs[1] = fabs(u2);
+      term = metal ? 0.0 : nll_term(dl, (double)g[0]) + nll_term(dh, (double)g[1]);
+    }
+  }
+}
+
+// Block reductions: FP64 sum into partial[lb], float max into wmax (atomicMax
+// on the bit pattern, valid for non-negative values).
+template <int NW>
+__device__ void block_reduce(double term, const float wabs[4], int nch, double* partial, int lb,
+                             uint32_t* wmax) {
+  __shared__ double s_sum[kFpBlock / 64];
+  __shared__ float s_max[kFpBlock / 64][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float m[4] = {wabs[0], wabs[1], wabs[2], wabs[3]};
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    term += __shfl_xor(term, o);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) m[c] = fmaxf(m[c], __shfl_xor(m[c], o));
+  }
+  if (lane == 0) {
+    s_sum[wv] = term;
+    for (int c = 0; c < 4; ++c) s_max[wv][c] = m[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    float mm[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < kFpBlock / 64; ++i) {
+      s += s_sum[i];
+      for (int c = 0; c < 4; ++c) mm[c] = fmaxf(mm[c], s_max[i][c]);
+    }
+    if (partial) partial[lb] = s;
+    if (wmax)
+      for (int c = 0; c < nch; ++c) atomicMax(&wmax[c], __float_as_uint(mm[c]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <typename T, bool Z3, int MODE>
+__global__ __launch_bounds__(kFpBlock) void k_fp(
+    GeomDev G, const typename Vec2<T>::type* __restrict__ cpy,
+    const typename Vec2<T>::type* __restrict__ cpx, const EBin<T>* __restrict__ eb, int nE,
+    const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
+    double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
+    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t ray = (int64_t)lb * kFpBlock + threadIdx.x;
+  const bool active = ray < G.R;
+  double term = 0.0;
+  T wabs[4] = {0, 0, 0, 0};
+  if (active) {
+    const int k = (int)(ray % G.n_cols);
+    const int rv = (int)(ray / G.n_cols);
+    const int r = rv % G.n_rows, v = rv / G.n_rows;
+    T l1, l2;
+    project_ray<T, Z3>(G, cpy, cpx, v, r, k, l1, l2);
+    if constexpr (MODE == PM_L) {
+      out[ray] = l1;
+      if (nout > 1) out[G.R + ray] = l2;
+    } else if constexpr (MODE == PM_TRACE) {
+      if (Tout) Tout[ray] = (double)l1;
+      mask_out[ray] = (double)l1 >= tthr ? 1 : 0;
+    } else {
+      poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, term, wabs);
+    }
+  }
+  if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
+    const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
+    block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax);
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kFpBlock) void k_poly(
+    int64_t R, const EBin<T>* __restrict__ eb, int nE, const T* __restrict__ l,
+    const float* __restrict__ d, const uint8_t* __restrict__ mask, const T* __restrict__ v,
+    T* __restrict__ w, T* __restrict__ gout, double* __restrict__ partial,
+    uint32_t* __restrict__ wmax) {
+  const int64_t ray = (int64_t)blockIdx.x * kFpBlock + threadIdx.x;
+  double term = 0.0;
+  T wabs[4] = {0, 0, 0, 0};
+  if (ray < R)
+    poly_epilogue<T, MODE>(eb, nE, l[ray], l[R + ray], ray, R, d, mask, v, w, gout, term, wabs);
+  const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
+  block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, wmax);
+}
+
+// max |w_c| over rays, per channel (for the fixed-point scale of a
+// backprojection of arbitrary weights).
+template <typename T>
+__global__ __launch_bounds__(kFpBlock) void k_absmax(int64_t R, int nch, const T* __restrict__ w,
+                                                     uint32_t* __restrict__ wmax) {
+  float m[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t i = (int64_t)blockIdx.x * kFpBlock + threadIdx.x; i < R;
+       i += (int64_t)gridDim.x * kFpBlock)
+    for (int c = 0; c < nch; ++c) m[c] = fmaxf(m[c], (float)fabs(w[c * R + i]));
+  block_reduce<4>(0.0, m, nch, nullptr, 0, wmax);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Deterministic FP64 sum of n partials into out[0] (one block of 1024).
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ p, int64_t n,
+                                                 double* __restrict__ out) {
+  __shared__ double s[1024];
+  double acc = 0.0, cmp = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) neumaier(acc, cmp, p[i]);
+  s[threadIdx.x] = acc + cmp;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Backprojection: tile-owned, fixed point in LDS
+// ---------------------------------------------------------------------------
+// Fixed-point formats:
+//   ACC_PACKED: 4 non-negative channels as two 64-bit words, each holding two
+//     unsigned 32-bit fields; scale_c = 2^31 / (h1 * max w_c), so no field
+//     can exceed 2^31 + (number of additions)/2 < 2^32 and no carry crosses
+//     fields.  Contributions are rounded half up.
+//   ACC_I64: one signed 64-bit word per channel, scale_c = 2^61 / (h1 * max|w_c|).
+// h1 is an upper bound of max_x sum_y h(x,y) computed from the geometry.
+template <typename T, bool Z3, int ACC, int NCH>
+__global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
+                                                 const uint32_t* __restrict__ wmax, double h1,
+                                                 T* __restrict__ b) {
+  extern __shared__ unsigned long long acc[];
+  constexpr int WPV = (ACC == ACC_PACKED) ? NCH / 2 : NCH;  // 64-bit words per voxel
+  __shared__ float s_kap[kViewBatch][4];
+  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_off[kViewBatch + 1];
+
+  const int t = blockIdx.x;
+  const int tix = t % TL.ntx, tiy = (t / TL.ntx) % TL.nty, tiz = t / (TL.ntx * TL.nty);
+  const int tx0 = tix * TL.tx, ty0 = tiy * TL.ty, tz0 = tiz * TL.tz;
+  const int tx1 = min(tx0 + TL.tx, G.nx), ty1 = min(ty0 + TL.ty, G.ny);
+  const int tz1 = min(tz0 + TL.tz, G.is3d ? G.nz : 1);
+  const int nvox = TL.tx * TL.ty * TL.tz;
+  for (int i = threadIdx.x; i < nvox * WPV; i += kBpBlock) acc[i] = 0ull;
+
+  double scale[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const float m = __uint_as_float(wmax[c]);
+    const double top = (ACC == ACC_PACKED) ? 2147483648.0 : 2305843009213693952.0;
+    scale[c] = (m > 0.f && h1 > 0.0) ? top / (h1 * (double)m) : 0.0;
+  }
+
+  // tile rectangle (mm) and axial range
+  const double X0 = G.x0 + tx0 * G.dx, X1 = G.x0 + tx1 * G.dx;
+  const double Y0 = G.y0 + ty0 * G.dy, Y1 = G.y0 + ty1 * G.dy;
+  const double Z0 = G.z0 + tz0 * G.dz, Z1 = G.z0 + tz1 * G.dz;
+  __syncthreads();
+
+  for (int vb0 = 0; vb0 < G.n_views; vb0 += kViewBatch) {
+    // channel coordinate of the 4 tile corners for each view of the batch
+    if (threadIdx.x < 4 * kViewBatch) {
+      const int j = threadIdx.x >> 2, cn = threadIdx.x & 3;
+      const int v = vb0 + j;
+      float kap = 0.f;
+      if (v < G.n_views) {
+        const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
+        const double px = (cn & 1) ? X1 : X0, py = (cn & 2) ? Y1 : Y0;
+        const double qx = px - G.sid * cb, qy = py - G.sid * sb;
+        const float cr = (float)(-cb * qy + sb * qx), dt = (float)(-cb * qx - sb * qy);
+        kap = atan2f(cr, dt) / (float)G.dgamma + (float)G.kc;
+      }
+      s_kap[j][cn] = kap;
+    }
+    __syncthreads();
+    if (threadIdx.x < kViewBatch) {
+      const int j = threadIdx.x, v = vb0 + j;
+      int kl = 0, nk = 0, rl = 0, nr = 0;
+      if (v < G.n_views) {
+        const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
+        const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
+        kl = max((int)ceilf(kmn - 0.01f), 0);
+        const int kh = min((int)floorf(kmx + 0.01f), G.n_cols - 1);
+        nk = max(kh - kl + 1, 0);
+        if (G.is3d) {
+          const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
+          const double zs = G.view[4 * v + 2];
+          const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
+          const double dmin = fmax(sqrt((sx - cx) * (sx - cx) + (sy - cy) * (sy - cy)), 1e-6);
+          const double fx = fmax(fabs(sx - X0), fabs(sx - X1)), fy = fmax(fabs(sy - Y0), fabs(sy - Y1));
+          const double dmax = sqrt(fx * fx + fy * fy);
+          const double za = (Z0 - zs) * G.sdd, zb = (Z1 - zs) * G.sdd;
+          const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
+          const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
+          rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
+          const int rh = min((int)floor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
+          nr = max(rh - rl + 1, 0);
+        } else {
+          nr = 1;
+        }
+      }
+      s_kl[j] = kl;
+      s_nk[j] = nk;
+      s_rl[j] = rl;
+      s_off[j] = nk * nr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int j = 0; j < kViewBatch; ++j) {
+        const int n = s_off[j];
+        s_off[j] = run;
+        run += n;
+      }
+      s_off[kViewBatch] = run;
+    }
+    __syncthreads();
+    const int total = s_off[kViewBatch];
+    for (int it = threadIdx.x; it < total; it += kBpBlock) {
+      int j = 0;
+#pragma unroll
+      for (int q = 1; q < kViewBatch; ++q) j += (it >= s_off[q]) ? 1 : 0;
+      const int loc = it - s_off[j];
+      const int nk = s_nk[j];
+      const int r = s_rl[j] + loc / nk, k = s_kl[j] + loc % nk;
+      const int v = vb0 + j;
+      Ray<T> ry;
+      if (!ray_setup<T>(G, v, r, k, (double)tx0, (double)ty0, (double)tz0, (double)tx1,
+                        (double)ty1, (double)tz1, ry))
+        continue;
+      const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
+      T ws[NCH];
+      double wsd[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        wsd[c] = (double)w[c * G.R + ray] * scale[c];
+        ws[c] = (T)wsd[c];
+      }
+      const int la = ry.ydrive ? ty0 : tx0, ha = ry.ydrive ? ty1 : tx1;
+      const int lbb = ry.ydrive ? tx0 : ty0, hb = ry.ydrive ? tx1 : ty1;
+      const int sa = ry.ydrive ? TL.tx : 1, sbs = ry.ydrive ? 1 : TL.tx;
+      const int txy = TL.tx * TL.ty;
+      auto visit = [&](int ia, int ib, int iw, T h) {
+        const int li = (iw - tz0) * txy + (ia - la) * sa + (ib - lbb) * sbs;
+        if constexpr (ACC == ACC_PACKED) {
+#pragma unroll
+          for (int q = 0; q < NCH / 2; ++q) {
+            const uint32_t f0 = (uint32_t)fma(h, ws[2 * q], (T)0.5);
+            const uint32_t f1 = (uint32_t)fma(h, ws[2 * q + 1], (T)0.5);
+            atomicAdd(&acc[li * WPV + q], ((unsigned long long)f1 << 32) | (unsigned long long)f0);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const long long q = __double2ll_rn((double)h * wsd[c]);
+            atomicAdd(&acc[li * WPV + c], (unsigned long long)q);
+          }
+        }
+      };
+      auto noflush = [&]() {};
+      walk<T, Z3>(ry, la, ha, lbb, hb, tz0, tz1, visit, noflush);
+    }
+    __syncthreads();
+  }
+
+  // write the tile
+  for (int i = threadIdx.x; i < nvox; i += kBpBlock) {
+    const int lx = i % TL.tx, ly = (i / TL.tx) % TL.ty, lz = i / (TL.tx * TL.ty);
+    const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
+    if (gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
+    const int64_t gi = ((int64_t)gz * G.ny + gy) * G.nx + gx;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      double val;
+      if constexpr (ACC == ACC_PACKED) {
+        const unsigned long long word = acc[i * WPV + c / 2];
+        const uint32_t f = (c & 1) ? (uint32_t)(word >> 32) : (uint32_t)(word & 0xffffffffull);
+        val = (double)f;
+      } else {
+        val = (double)(long long)acc[i * WPV + c];
+      }
+      b[c * G.V + gi] = scale[c] > 0.0 ? (T)(val / scale[c]) : (T)0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update and packing (32x32 tiles, LDS transpose for the x-major copy)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(GeomDev G, double* __restrict__ c64,
+                                                const T* __restrict__ b, double iz1, double iz2,
+                                                T* __restrict__ c_proj,
+                                                typename Vec2<T>::type* __restrict__ cpy,
+                                                typename Vec2<T>::type* __restrict__ cpx) {
+  using T2 = typename Vec2<T>::type;
+  __shared__ T2 tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+  const int64_t V = G.V;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ix = bx * 32 + tx, iy = by * 32 + ty + 8 * j;
+    if (ix < G.nx && iy < G.ny) {
+      const int64_t idx = ((int64_t)z * G.ny + iy) * G.nx + ix;
+      double c1 = c64[idx], c2 = c64[V + idx];
+      if (b) {
+        const double bt1 = (double)b[idx], bt2 = (double)b[V + idx];
+        const double bh1 = (double)b[2 * V + idx], bh2 = (double)b[3 * V + idx];
+        if (bt1 > 0.0 && bh1 > 0.0) c1 -= log(bt1 / bh1) * iz1;
+        if (bt2 > 0.0 && bh2 > 0.0) c2 -= log(bt2 / bh2) * iz2;
+        c64[idx] = c1;
+        c64[V + idx] = c2;
+      }
+      T2 p;
+      p.x = (T)c1;
+      p.y = (T)c2;
+      if (c_proj) {
+        c_proj[idx] = p.x;
+        c_proj[V + idx] = p.y;
+      }
+      if (cpy) cpy[idx] = p;
+      tile[ty + 8 * j][tx] = p;
+    }
+  }
+  if (!cpx) return;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ix = bx * 32 + ty + 8 * j, iy = by * 32 + tx;
+    if (ix < G.nx && iy < G.ny) cpx[((int64_t)z * G.nx + ix) * G.ny + iy] = tile[tx][ty + 8 * j];
+  }
+}
+
+// planar [n_ch][V] (T, or uint8 when U8) -> packed natural and transposed copies
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_pack(GeomDev G, const S* __restrict__ c, int n_ch,
+                                              typename Vec2<T>::type* __restrict__ cpy,
+                                              typename Vec2<T>::type* __restrict__ cpx) {
+  using T2 = typename Vec2<T>::type;
+  __shared__ T2 tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ix = bx * 32 + tx, iy = by * 32 + ty + 8 * j;
+    if (ix < G.nx && iy < G.ny) {
+      const int64_t idx = ((int64_t)z * G.ny + iy) * G.nx + ix;
+      T2 p;
+      p.x = (T)c[idx];
+      p.y = n_ch > 1 ? (T)c[G.V + idx] : (T)0;
+      cpy[idx] = p;
+      tile[ty + 8 * j][tx] = p;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ix = bx * 32 + ty + 8 * j, iy = by * 32 + tx;
+    if (ix < G.nx && iy < G.ny) cpx[((int64_t)z * G.nx + ix) * G.ny + iy] = tile[tx][ty + 8 * j];
+  }
+}
+
+inline dim3 image_grid(const deam_plan* p) {
+  return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8, bool dbl,
+                       void* cp_y, void* cp_x, hipStream_t st) {
+  if (dbl) {
+    if (from_u8)
+      hipLaunchKernelGGL((k_pack<double, uint8_t>), image_grid(p), dim3(256), 0, st, p->gd,
+                         (const uint8_t*)c, n_ch, (double2*)cp_y, (double2*)cp_x);
+    else
+      hipLaunchKernelGGL((k_pack<double, double>), image_grid(p), dim3(256), 0, st, p->gd,
+                         (const double*)c, n_ch, (double2*)cp_y, (double2*)cp_x);
+  } else {
+    hipLaunchKernelGGL((k_pack<float, float>), image_grid(p), dim3(256), 0, st, p->gd,
+                       (const float*)c, n_ch, (float2*)cp_y, (float2*)cp_x);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
+                        const uint8_t* mask, void* out, double* partial, uint32_t* wmax,
+                        double tthr, uint8_t* mask_out, double* Tout, hipStream_t st, int nout = 2) {
+  using T2 = typename Vec2<T>::type;
+  const dim3 grid((unsigned)p->fp_blocks), blk(kFpBlock);
+  const EBin<T>* eb = (const EBin<T>*)p->d_energy;
+  if (p->gd.is3d)
+    hipLaunchKernelGGL((k_fp<T, true, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y,
+                       (const T2*)cp_x, eb, p->nE, d, mask, (T*)out, partial, wmax, tthr,
+                       mask_out, Tout, nout);
+  else
+    hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y,
+                       (const T2*)cp_x, eb, p->nE, d, mask, (T*)out, partial, wmax, tthr,
+                       mask_out, Tout, nout);
+}
+
+hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
+                          int n_out, hipStream_t st) {
+  if (p->precision == DEAM_PREC_FP64)
+    fp_dispatch<double, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, nullptr, 0.0, nullptr,
+                              nullptr, st, n_out);
+  else
+    fp_dispatch<float, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, nullptr, 0.0, nullptr,
+                             nullptr, st, n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* cp_x, double t,
+                              uint8_t* mask, double* T, hipStream_t st) {
+  fp_dispatch<double, PM_TRACE>(p, cp_y, cp_x, nullptr, nullptr, nullptr, nullptr, nullptr, t,
+                                mask, T, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
+                          const uint8_t* mask, int mode, void* w, double* partial,
+                          uint32_t* wmax, hipStream_t st) {
+  const bool dbl = p->precision == DEAM_PREC_FP64;
+  if (mode == PM_AM) {
+    if (dbl) fp_dispatch<double, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+    else fp_dispatch<float, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+  } else if (mode == PM_GRAD) {
+    if (dbl) fp_dispatch<double, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+    else fp_dispatch<float, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static void poly_dispatch(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
+                          int mode, const void* v, void* w, void* g, double* partial,
+                          uint32_t* wmax, hipStream_t st) {
+  const int64_t R = p->gd.R;
+  const dim3 grid((unsigned)((R + kFpBlock - 1) / kFpBlock)), blk(kFpBlock);
+  const EBin<T>* eb = (const EBin<T>*)p->d_energy;
+  if (mode == PM_AM)
+    hipLaunchKernelGGL((k_poly<T, PM_AM>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
+                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+  else if (mode == PM_GRAD)
+    hipLaunchKernelGGL((k_poly<T, PM_GRAD>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d,
+                       mask, (const T*)v, (T*)w, (T*)g, partial, wmax);
+  else
+    hipLaunchKernelGGL((k_poly<T, PM_VJP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
+                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+}
+
+hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
+                       int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
+                       hipStream_t st) {
+  if (p->precision == DEAM_PREC_FP64)
+    poly_dispatch<double>(p, l, d, mask, mode, v, w, g, partial, wmax, st);
+  else
+    poly_dispatch<float>(p, l, d, mask, mode, v, w, g, partial, wmax, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* ptr, uint32_t v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ptr, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmax,
+                         hipStream_t st) {
+  const int64_t R = p->gd.R;
+  const unsigned nb = (unsigned)std::min<int64_t>((R + kFpBlock - 1) / kFpBlock, 2048);
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_absmax<double>, dim3(nb), dim3(kFpBlock), 0, st, R, n_ch,
+                       (const double*)w, wmax);
+  else
+    hipLaunchKernelGGL(k_absmax<float>, dim3(nb), dim3(kFpBlock), 0, st, R, n_ch,
+                       (const float*)w, wmax);
+  return hipGetLastError();
+}
+
+template <typename T, bool Z3, int ACC, int NCH>
+static hipError_t bp_go(const deam_plan* p, const Tiling& TL, const void* w, const uint32_t* wmax,
+                        void* b, hipStream_t st) {
+  constexpr int WPV = (ACC == ACC_PACKED) ? NCH / 2 : NCH;
+  const size_t lds = (size_t)TL.tx * TL.ty * TL.tz * WPV * 8;
+  const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
+  auto kern = k_bp<T, Z3, ACC, NCH>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nt), dim3(kBpBlock), lds, st, p->gd, TL, (const T*)w, wmax,
+                     p->h1_bound, (T*)b);
+  return hipGetLastError();
+}
+
+template <typename T, bool Z3>
+static hipError_t bp_by_channels(const deam_plan* p, const void* w, int n_ch, int acc,
+                                 const uint32_t* wmax, void* b, hipStream_t st) {
+  if (acc == ACC_PACKED) {
+    if (n_ch != 4) return hipErrorInvalidValue;
+    return bp_go<T, Z3, ACC_PACKED, 4>(p, p->tile_packed, w, wmax, b, st);
+  }
+  switch (n_ch) {
+    case 1: return bp_go<T, Z3, ACC_I64, 1>(p, p->tile_i64[1], w, wmax, b, st);
+    case 2: return bp_go<T, Z3, ACC_I64, 2>(p, p->tile_i64[2], w, wmax, b, st);
+    case 4: return bp_go<T, Z3, ACC_I64, 4>(p, p->tile_i64[4], w, wmax, b, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, int acc,
+                              const uint32_t* wmax, void* b, hipStream_t st) {
+  const bool dbl = p->precision == DEAM_PREC_FP64;
+  if (dbl) {
+    if (acc == ACC_PACKED) return hipErrorInvalidValue;
+    return p->gd.is3d ? bp_by_channels<double, true>(p, w, n_ch, acc, wmax, b, st)
+                      : bp_by_channels<double, false>(p, w, n_ch, acc, wmax, b, st);
+  }
+  return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, acc, wmax, b, st)
+                    : bp_by_channels<float, false>(p, w, n_ch, acc, wmax, b, st);
+}
+
+hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
+                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st) {
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_update<double>, image_grid(p), dim3(256), 0, st, p->gd, c64,
+                       (const double*)b, 1.0 / z1, 1.0 / z2, (double*)c_proj, (double2*)cp_y,
+                       (double2*)cp_x);
+  else
+    hipLaunchKernelGGL(k_update<float>, image_grid(p), dim3(256), 0, st, p->gd, c64,
+                       (const float*)b, 1.0 / z1, 1.0 / z2, (float*)c_proj, (float2*)cp_y,
+                       (float2*)cp_x);
+  return hipGetLastError();
+}
+
+}  // namespace deam

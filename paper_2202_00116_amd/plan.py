@@ -1,0 +1,177 @@
+"""Python face of the C ABI: one Plan per scanner geometry and spectrum pair.
+
+Every method marshals torch device tensors into the matching ``deam_*`` call
+of libdeam.so on torch's current stream; all arithmetic runs in the HIP
+kernels.  Tensors follow the layouts of include/deam.h: images [n_ch, V]
+and sinograms [n_ch, R], channel-major, C-contiguous, on the plan's device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A DEAM plan (geometry tables and energy table on the device).
+
+    geom: any object with the fields of ``deam_geometry`` (e.g.
+    ``workloads.Geometry``); I0, mu: (2, n_energy) float64 arrays;
+    precision: "mixed" (FP32 projections, FP64 reductions and update) or "fp64".
+    """
+
+    def __init__(self, geom, I0, mu, precision="mixed"):
+        self.lib = L.load()
+        if precision not in ("mixed", "fp64"):
+            raise ValueError("precision must be 'mixed' or 'fp64'")
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "mixed" else torch.float64
+        self.geom = geom
+        g = L.DeamGeometry(int(geom.kind), geom.nx, geom.ny, geom.nz, geom.dx, geom.dy, geom.dz,
+                           geom.n_views, geom.n_rows, geom.n_cols, geom.sid, geom.sdd,
+                           geom.dgamma, geom.col_offset, geom.drow_iso, geom.beta0,
+                           geom.views_per_rot, geom.feed_per_rot)
+        I0 = np.ascontiguousarray(I0, dtype=np.float64)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        if I0.shape != mu.shape or I0.ndim != 2 or I0.shape[0] != 2:
+            raise ValueError("I0 and mu must both have shape (2, n_energy)")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._p = C.c_void_p()
+        L.check(self.lib.deam_plan_create(C.byref(g), I0.shape[1], I0.ctypes.data_as(C.c_void_p),
+                                          mu.ctypes.data_as(C.c_void_p),
+                                          L.PREC_MIXED if precision == "mixed" else L.PREC_FP64,
+                                          C.byref(self._p)))
+        R, V = C.c_int64(), C.c_int64()
+        L.check(self.lib.deam_plan_sizes(self._p, C.byref(R), C.byref(V)))
+        self.R, self.V = R.value, V.value
+        self._ws = {}
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            try:
+                self.lib.deam_plan_destroy(p)
+            except Exception:
+                pass
+            self._p = None
+
+    # -- workspace -------------------------------------------------------------
+    def workspace_bytes(self, op):
+        n = C.c_size_t()
+        L.check(self.lib.deam_workspace_size(self._p, op, C.byref(n)))
+        return n.value
+
+    def workspace(self, op):
+        """Cached 256-byte aligned device workspace for an operation."""
+        need = self.workspace_bytes(op)
+        buf = self._ws.get(op)
+        if buf is None or buf[2] < need:
+            raw = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            self._ws[op] = (raw, off, need)
+            buf = self._ws[op]
+        raw, off, n = buf
+        return C.c_void_p(raw.data_ptr() + off), C.c_size_t(n)
+
+    def _check(self, t, shape, dtype, name):
+        if t is None:
+            return
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)}, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+
+    # -- operations ----------------------------------------------------------------
+    def metal_trace(self, M, t, want_T=False):
+        """mask[y] = (sum_x h(x,y) M(x) >= t); optionally the FP64 trace T."""
+        self._check(M, (self.V,), torch.uint8, "M")
+        mask = torch.empty(self.R, dtype=torch.uint8, device=self.device)
+        T = torch.empty(self.R, dtype=torch.float64, device=self.device) if want_T else None
+        ws, n = self.workspace(L.OP_METAL_TRACE)
+        L.check(self.lib.deam_metal_trace(self._p, _ptr(M), float(t), _ptr(mask), _ptr(T), ws, n,
+                                          _stream()))
+        return (mask, T) if want_T else mask
+
+    def forward(self, c):
+        """l[c] = H c[c] for c of shape (n_ch, V), n_ch in {1, 2}."""
+        n_ch = c.shape[0]
+        self._check(c, (n_ch, self.V), self.dtype, "c")
+        l = torch.empty((n_ch, self.R), dtype=self.dtype, device=self.device)
+        ws, n = self.workspace(L.OP_FORWARD)
+        L.check(self.lib.deam_forward(self._p, _ptr(c), n_ch, _ptr(l), ws, n, _stream()))
+        return l
+
+    def poly_mean(self, l, d, mask=None, mode=L.W_AM, v=None, want_g=False, want_obj=False):
+        self._check(l, (2, self.R), self.dtype, "l")
+        if mode != L.W_VJP:
+            self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(v, (2, self.R), self.dtype, "v")
+        nw = 4 if mode == L.W_AM else 2
+        w = torch.empty((nw, self.R), dtype=self.dtype, device=self.device)
+        g = torch.empty((2, self.R), dtype=self.dtype, device=self.device) if want_g else None
+        obj = torch.empty(1, dtype=torch.float64, device=self.device) if want_obj else None
+        ws, n = self.workspace(L.OP_POLY_MEAN)
+        L.check(self.lib.deam_poly_mean(self._p, _ptr(l), _ptr(d), _ptr(mask), mode, _ptr(v),
+                                        _ptr(w), _ptr(g), _ptr(obj), ws, n, _stream()))
+        return w, g, obj
+
+    def backproject(self, w):
+        """b[c] = H^T w[c] for w of shape (n_ch, R), n_ch in {1, 2, 4}."""
+        n_ch = w.shape[0]
+        self._check(w, (n_ch, self.R), self.dtype, "w")
+        b = torch.empty((n_ch, self.V), dtype=self.dtype, device=self.device)
+        ws, n = self.workspace(L.OP_BACKPROJECT)
+        L.check(self.lib.deam_backproject(self._p, _ptr(w), n_ch, _ptr(b), ws, n, _stream()))
+        return b
+
+    def update(self, c64, b, Z, want_proj=False):
+        """In-place c_i <- c_i - ln(b~_i / b^_i) / Z_i; returns the projection copy if asked."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(b, (4, self.V), self.dtype, "b")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        cp = torch.empty((2, self.V), dtype=self.dtype, device=self.device) if want_proj else None
+        L.check(self.lib.deam_update(self._p, _ptr(c64), _ptr(cp), _ptr(b),
+                                     Zh.ctypes.data_as(C.c_void_p), _stream()))
+        return cp
+
+    def iterate(self, c64, d, mask, Z, n_iter, obj_hist=None):
+        """n_iter DEAM iterations in place on c64; obj_hist (device float64 [n_iter])
+        receives the masked I-divergence at each iterate."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        ws, n = self.workspace(L.OP_ITERATE)
+        L.check(self.lib.deam_iterate(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+                                      Zh.ctypes.data_as(C.c_void_p), int(n_iter), _ptr(obj_hist),
+                                      ws, n, _stream()))
+        return c64
+
+    def iterate_timed(self, c64, d, mask, Z, n_iter, obj_hist=None):
+        """iterate() plus per-kernel device times (ms summed over the iterations):
+        dict(fp_poly, backproject, update, loop).  Synchronises the stream."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        ws, n = self.workspace(L.OP_ITERATE)
+        ms = (C.c_float * 4)()
+        L.check(self.lib.deam_iterate_timed(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+                                            Zh.ctypes.data_as(C.c_void_p), int(n_iter),
+                                            _ptr(obj_hist), ws, n, _stream(), ms))
+        return dict(fp_poly=ms[0], backproject=ms[1], update=ms[2], loop=ms[3])

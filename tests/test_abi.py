@@ -1,0 +1,94 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/deam.h declares, and rejects bad arguments with status codes before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "deam.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(deam_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2202_00116_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2202_00116_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_function(lib):
+    from paper_2202_00116_amd import _lib
+    names = header_functions()
+    assert set(names) == set(_lib.EXPORTS), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def geometry(**kw):
+    from paper_2202_00116_amd import _lib
+    base = dict(kind=0, nx=64, ny=64, nz=1, dx=1.0, dy=1.0, dz=1.0, n_views=64, n_rows=1,
+                n_cols=96, sid=570.0, sdd=1040.0, dgamma=0.002, col_offset=0.0, drow_iso=1.0,
+                beta0=0.0, views_per_rot=64.0, feed_per_rot=0.0)
+    base.update(kw)
+    return _lib.DeamGeometry(**base)
+
+
+def create(lib, g, I0=None, mu=None, prec=0, n_e=4):
+    I0 = np.ones((2, n_e)) if I0 is None else I0
+    mu = np.full((2, n_e), 0.02) if mu is None else mu
+    out = C.c_void_p()
+    rc = lib.deam_plan_create(C.byref(g), I0.shape[1], I0.ctypes.data_as(C.c_void_p),
+                              mu.ctypes.data_as(C.c_void_p), prec, C.byref(out))
+    return rc, out
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(kind=5), -3),
+    (dict(nx=0), -2),
+    (dict(nz=2), -2),                      # a fan-beam geometry has one slice
+    (dict(n_rows=3), -2),
+    (dict(dx=-1.0), -3),
+    (dict(dgamma=0.0), -3),
+    (dict(sid=40.0), -3),                  # source inside the grid
+    (dict(sdd=600.0), -3),                 # detector inside the grid
+    (dict(views_per_rot=0.0), -3),
+    (dict(kind=1, nz=8, n_rows=4, drow_iso=0.0), -3),
+])
+def test_bad_geometry(lib, kw, code):
+    rc, out = create(lib, geometry(**kw))
+    assert rc == code
+    assert out.value is None
+    assert len(lib.deam_last_error()) > 0
+
+
+def test_bad_spectra_and_precision(lib):
+    g = geometry()
+    assert create(lib, g, I0=-np.ones((2, 4)))[0] == -7
+    assert create(lib, g, mu=np.full((2, 4), np.nan))[0] == -7
+    assert create(lib, g, prec=3)[0] == -7
+    rc = lib.deam_plan_create(C.byref(g), 4, None, None, 0, C.byref(C.c_void_p()))
+    assert rc == -1
+    assert lib.deam_plan_create(C.byref(g), 4, None, None, 0, None) == -1
+
+
+def test_null_plan_calls(lib):
+    n = C.c_size_t()
+    assert lib.deam_workspace_size(None, 0, C.byref(n)) == -1
+    assert lib.deam_plan_destroy(None) == -1
+    assert lib.deam_forward(None, None, 2, None, None, 0, None) == -1
+    assert lib.deam_backproject(None, None, 4, None, None, 0, None) == -1
+    assert lib.deam_iterate(None, None, None, None, None, 1, None, None, 0, None) == -1
+    assert lib.deam_update(None, None, None, None, None, None) == -1
+    assert lib.deam_poly_mean(None, None, None, None, 0, None, None, None, None, None, 0, None) == -1
+    assert lib.deam_metal_trace(None, None, 0.5, None, None, None, 0, None) == -1
+    assert b"NULL" in lib.deam_last_error()

@@ -1,0 +1,194 @@
+"""GPU parity: every C-ABI call against the FP64 CPU oracle on the same seeded
+inputs.  Tolerances (relative L2 over the whole result unless stated):
+  mixed precision: projections, g and weights <= 1e-5; images after 20
+                   iterations <= 1e-4; masks bit-exact;
+  fp64:            <= 1e-10 (projections, weights, images).
+"""
+import numpy as np
+import pytest
+import torch
+
+from workloads import make_inputs, geometry_for
+from workloads import geometry as G
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def odd_fan():
+    """Non-square grid, anisotropic pixels, channel offset, odd sizes."""
+    return G.Geometry(kind=0, nx=45, ny=37, nz=1, dx=1.1, dy=0.9, dz=1.0, n_views=37, n_rows=1,
+                      n_cols=71, sid=300.0, sdd=560.0, dgamma=G.fan_dgamma(45, 37, 1.1, 0.9, 300.0, 71) * 1.05,
+                      col_offset=0.25, drow_iso=1.0, beta0=0.3, views_per_rot=37.0, feed_per_rot=0.0)
+
+
+def odd_helix():
+    return G.Geometry(kind=1, nx=35, ny=29, nz=11, dx=1.0, dy=1.2, dz=0.9, n_views=50, n_rows=5,
+                      n_cols=61, sid=250.0, sdd=480.0, dgamma=G.fan_dgamma(35, 29, 1.0, 1.2, 250.0, 61),
+                      col_offset=-0.3, drow_iso=1.5, beta0=0.7, views_per_rot=24.0, feed_per_rot=4.0)
+
+
+GEOMS = {
+    "fan64": lambda: geometry_for("fan64"),
+    "fan128": lambda: geometry_for("fan128"),
+    "helical_small": lambda: geometry_for("helical_small"),
+    "odd_fan": odd_fan,
+    "odd_helix": odd_helix,
+}
+
+
+@pytest.fixture(scope="module")
+def spectra():
+    inp = make_inputs("fan64", with_data=False)
+    return inp["I0"], inp["mu"]
+
+
+def plan_for(g, spectra, prec):
+    from paper_2202_00116_amd.plan import Plan
+    return Plan(g, spectra[0], spectra[1], prec)
+
+
+@pytest.mark.parametrize("gname", list(GEOMS))
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_forward(orc, spectra, gname, prec, tol):
+    g = GEOMS[gname]()
+    plan = plan_for(g, spectra, prec)
+    rng = np.random.default_rng(1)
+    c = rng.uniform(0.0, 1.0, (2, g.n_voxels))
+    ref = orc.forward(g, c)
+    l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
+    # the oracle is fed the values the GPU sees (rounded to the plan precision)
+    ref = orc.forward(g, c.astype(np.float32).astype(np.float64)) if prec == "mixed" else ref
+    print(gname, prec, "forward rel", rel(l, ref))
+    assert rel(l, ref) <= tol
+    l1 = plan.forward(torch.tensor(c[:1], dtype=plan.dtype, device=DEV)).cpu().numpy()
+    assert rel(l1, ref[:1]) <= tol
+
+
+@pytest.mark.parametrize("gname", list(GEOMS))
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+@pytest.mark.parametrize("nch", [1, 2, 4])
+def test_backproject(orc, spectra, gname, prec, tol, nch):
+    g = GEOMS[gname]()
+    plan = plan_for(g, spectra, prec)
+    rng = np.random.default_rng(2)
+    # non-negative weights (as the AM weights are): error relative to the result
+    w = rng.uniform(0.0, 1.0, (nch, g.n_rays))
+    if prec == "mixed":
+        w = w.astype(np.float32).astype(np.float64)
+    ref = orc.backproject(g, w)
+    b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
+    print(gname, prec, nch, "backproject rel", rel(b, ref))
+    assert rel(b, ref) <= tol
+    # signed weights: the sums cancel, so the error is measured against H^T |w|
+    ws = rng.standard_normal((nch, g.n_rays))
+    if prec == "mixed":
+        ws = ws.astype(np.float32).astype(np.float64)
+    ref = orc.backproject(g, ws)
+    scale = np.linalg.norm(orc.backproject(g, np.abs(ws)))
+    b = plan.backproject(torch.tensor(ws, dtype=plan.dtype, device=DEV)).cpu().numpy()
+    print(gname, prec, nch, "signed backproject err / |H^T|w||", np.linalg.norm(b - ref) / scale)
+    assert np.linalg.norm(b - ref) <= tol * scale
+
+
+@pytest.mark.parametrize("gname", ["fan64", "helical_small", "odd_helix"])
+def test_adjoint_identity_gpu(spectra, gname):
+    g = GEOMS[gname]()
+    plan = plan_for(g, spectra, "mixed")
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.uniform(0, 1, (2, g.n_voxels)), dtype=torch.float32, device=DEV)
+    y = torch.tensor(rng.uniform(0, 1, (2, g.n_rays)), dtype=torch.float32, device=DEV)
+    lhs = (plan.forward(x).double() * y.double()).sum().item()
+    rhs = (x.double() * plan.backproject(y).double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_poly_mean(orc, prec, tol, mode):
+    inp = make_inputs("fan64")
+    g = inp["geom"]
+    plan = plan_for(g, (inp["I0"], inp["mu"]), prec)
+    rng = np.random.default_rng(4)
+    l = orc.forward(g, inp["c0"] * rng.uniform(0.8, 1.2, inp["c0"].shape))
+    if prec == "mixed":
+        l = l.astype(np.float32).astype(np.float64)
+    mask = (rng.random(g.n_rays) < 0.2).astype(np.uint8)
+    w_o, g_o, obj_o = orc.poly_mean(inp["I0"], inp["mu"], l, inp["d"], mask, mode=mode)
+    w, gg, obj = plan.poly_mean(torch.tensor(l, dtype=plan.dtype, device=DEV),
+                                torch.tensor(inp["d"], device=DEV),
+                                torch.tensor(mask, device=DEV), mode=mode, want_g=True,
+                                want_obj=True)
+    assert rel(gg.cpu().numpy(), g_o) <= tol
+    assert rel(w.cpu().numpy(), w_o) <= tol * (10 if mode == 1 else 1)
+    assert abs(obj.item() - obj_o.sum()) <= (1e-6 if prec == "mixed" else 1e-10) * abs(obj_o.sum())
+
+
+@pytest.mark.parametrize("name", ["fan64", "fan128", "helical_small"])
+def test_metal_trace_bit_exact(orc, name):
+    inp = make_inputs(name, with_data=False)
+    g = inp["geom"]
+    mask_o, T_o = orc.metal_trace(g, inp["metal"], inp["t"])
+    plan = plan_for(g, (inp["I0"], inp["mu"]), "mixed")
+    mask, T = plan.metal_trace(torch.tensor(inp["metal"], device=DEV), inp["t"], want_T=True)
+    T = T.cpu().numpy()
+    margin = np.abs(T_o - inp["t"]).min()
+    print(name, "trace margin", margin, "T err", np.abs(T - T_o).max())
+    assert np.abs(T - T_o).max() < 1e-10
+    assert np.array_equal(mask.cpu().numpy(), mask_o)
+    assert mask_o.sum() > 0
+
+
+@pytest.mark.parametrize("name,n", [("fan64", 20), ("fan128", 20), ("helical_small", 8)])
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_iterate(orc, name, n, prec, tol):
+    inp = make_inputs(name)
+    g = inp["geom"]
+    mask_o, _ = orc.metal_trace(g, inp["metal"], inp["t"])
+    c_o, h_o = orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], inp["c0"], n)
+    plan = plan_for(g, (inp["I0"], inp["mu"]), prec)
+    c = torch.tensor(inp["c0"], device=DEV)
+    hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+    plan.iterate(c, torch.tensor(inp["d"], device=DEV), torch.tensor(mask_o, device=DEV),
+                 inp["Z"], n, hist)
+    c = c.cpu().numpy()
+    h = hist.cpu().numpy()
+    print(name, prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
+    assert rel(c, c_o) <= tol
+    assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
+
+
+def test_iterate_is_deterministic_and_resumable(spectra):
+    inp = make_inputs("fan64")
+    g = inp["geom"]
+    plan = plan_for(g, (inp["I0"], inp["mu"]), "mixed")
+    d = torch.tensor(inp["d"], device=DEV)
+    c_a = torch.tensor(inp["c0"], device=DEV)
+    plan.iterate(c_a, d, None, inp["Z"], 6)
+    c_b = torch.tensor(inp["c0"], device=DEV)
+    plan.iterate(c_b, d, None, inp["Z"], 3)
+    plan.iterate(c_b, d, None, inp["Z"], 3)
+    assert torch.equal(c_a, c_b)
+    w = torch.rand((4, g.n_rays), device=DEV)
+    assert torch.equal(plan.backproject(w), plan.backproject(w))
+
+
+def test_update(orc, spectra):
+    g = geometry_for("fan64")
+    plan = plan_for(g, spectra, "fp64")
+    rng = np.random.default_rng(6)
+    b = rng.uniform(0.5, 2.0, (4, g.n_voxels))
+    b[0, :10] = 0.0
+    b[3, 20:30] = 0.0
+    c = rng.standard_normal((2, g.n_voxels))
+    Z = np.array([7.0, 30.0])
+    ref = orc.update(b, Z, c)
+    ct = torch.tensor(c, device=DEV)
+    plan.update(ct, torch.tensor(b, device=DEV), Z)
+    assert np.abs(ct.cpu().numpy() - ref).max() < 1e-14
