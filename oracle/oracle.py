@@ -14,6 +14,7 @@ Each function mirrors one step of the DEAM hot path:
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -36,15 +37,21 @@ class OrcGeom(C.Structure):
                 ("feed_per_rot", C.c_double)]
 
 
+def compile_library(src, out):
+    """gcc build of an oracle source file into a shared library."""
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
+                           "-shared", "-fno-fast-math", "-ffp-contract=off",
+                           "-I", _HERE, "-o", out, src, "-lm"])
+    return out
+
+
 def build(force=False):
     """Compile liboracle.so with gcc (FP64, OpenMP, no fast-math)."""
     src = os.path.join(_HERE, "deam_oracle.c")
     if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
-                           "-shared", "-fno-fast-math", "-ffp-contract=off", "-o", tmp,
-                           src, "-lm"])
+    compile_library(src, tmp)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -57,33 +64,50 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        P = np.ctypeslib.ndpointer
-        d1 = P(dtype=np.float64, flags="C_CONTIGUOUS")
-        u1 = P(dtype=np.uint8, flags="C_CONTIGUOUS")
-        i1 = P(dtype=np.int64, flags="C_CONTIGUOUS")
-        G = C.POINTER(OrcGeom)
-        L.orc_num_threads.restype = C.c_int
-        L.orc_ray.argtypes = [G, C.c_long, d1, d1]
-        L.orc_siddon_ray.argtypes = [G, d1, d1, i1, d1, C.c_int]
-        L.orc_siddon_ray.restype = C.c_int
-        L.orc_forward.argtypes = [G, C.c_int, d1, d1]
-        L.orc_forward_rays.argtypes = [G, C.c_int, d1, C.c_long, i1, d1]
-        L.orc_backproject.argtypes = [G, C.c_int, d1, d1]
-        L.orc_poly_mean.argtypes = [C.c_long, C.c_int, d1, d1, d1, d1, C.c_void_p, C.c_int,
-                                    C.c_void_p, d1, C.c_void_p, C.c_void_p]
-        L.orc_sum.argtypes = [C.c_long, d1]
-        L.orc_sum.restype = C.c_double
-        L.orc_update.argtypes = [C.c_long, d1, d1, d1]
-        L.orc_metal_trace.argtypes = [G, u1, C.c_double, u1, C.c_void_p]
-        L.orc_iterate.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
-        L.orc_iterate.restype = C.c_int
-        L.orc_objective.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int]
-        L.orc_objective.restype = C.c_double
-        L.orc_nll_grad.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_void_p]
-        L.orc_nll_grad.restype = C.c_double
-        _lib = L
+        _lib = _setup(C.CDLL(LIB_PATH))
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path):
+    """Temporarily route every oracle call to another build of deam_oracle.c
+    (used by the tests that plant mistakes in a copy of the oracle)."""
+    global _lib
+    saved = lib()
+    _lib = _setup(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _setup(L):
+    """Declare the argument types of the oracle entry points."""
+    P = np.ctypeslib.ndpointer
+    d1 = P(dtype=np.float64, flags="C_CONTIGUOUS")
+    u1 = P(dtype=np.uint8, flags="C_CONTIGUOUS")
+    i1 = P(dtype=np.int64, flags="C_CONTIGUOUS")
+    G = C.POINTER(OrcGeom)
+    L.orc_num_threads.restype = C.c_int
+    L.orc_ray.argtypes = [G, C.c_long, d1, d1]
+    L.orc_siddon_ray.argtypes = [G, d1, d1, i1, d1, C.c_int]
+    L.orc_siddon_ray.restype = C.c_int
+    L.orc_forward.argtypes = [G, C.c_int, d1, d1]
+    L.orc_forward_rays.argtypes = [G, C.c_int, d1, C.c_long, i1, d1]
+    L.orc_backproject.argtypes = [G, C.c_int, d1, d1]
+    L.orc_poly_mean.argtypes = [C.c_long, C.c_int, d1, d1, d1, d1, C.c_void_p, C.c_int,
+                                C.c_void_p, d1, C.c_void_p, C.c_void_p]
+    L.orc_sum.argtypes = [C.c_long, d1]
+    L.orc_sum.restype = C.c_double
+    L.orc_update.argtypes = [C.c_long, d1, d1, d1]
+    L.orc_metal_trace.argtypes = [G, u1, C.c_double, u1, C.c_void_p]
+    L.orc_iterate.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
+    L.orc_iterate.restype = C.c_int
+    L.orc_objective.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int]
+    L.orc_objective.restype = C.c_double
+    L.orc_nll_grad.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_void_p]
+    L.orc_nll_grad.restype = C.c_double
+    return L
 
 
 def num_threads():

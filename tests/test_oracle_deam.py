@@ -130,30 +130,36 @@ def test_masked_idiv_nonincreasing(orc, name, n, use_mask):
 
 
 def test_monoenergetic_matches_textbook_am(orc):
-    """T11: one material and one energy bin reduce DEAM to the alternating
-    minimisation algorithm for transmission tomography:
-        c <- c - ln( H^T d / H^T (I0 exp(-mu H c)) ) / Z,
+    """T11: one energy bin reduces DEAM to the alternating minimisation
+    algorithm for transmission tomography.  With one bin mu_i cancels in the
+    ratio of the backprojections, so every component moves by the same log
+    ratio, each with its own normaliser:
+        q = I0 exp(-H (mu_1 c_1 + mu_2 c_2)),
+        c_i <- c_i - ln( H^T d / H^T q ) / Z_i,
     computed here with the brute-force dense H."""
     g = small_fan()
     S, P = ray_endpoints(g)
     H = np.stack([ray_row(g, S[i], P[i]) for i in range(g.n_rays)])
     rng = np.random.default_rng(11)
-    mu0 = 0.3
-    c_true = rng.uniform(0.5, 1.5, g.n_voxels)
+    mu1, mu2 = 0.3, 0.12
+    c_true = np.stack([rng.uniform(0.5, 1.5, g.n_voxels), rng.uniform(0.0, 0.5, g.n_voxels)])
     I0 = np.array([[1e4], [0.0]])
-    mu = np.array([[mu0], [0.0]])
-    d = np.stack([rng.poisson(1e4 * np.exp(-mu0 * (H @ c_true))).astype(float), np.zeros(g.n_rays)])
-    Z = np.array([2 * mu0 * g.box_diagonal(), 1.0])
-    c0 = np.stack([np.full(g.n_voxels, 1.0), np.full(g.n_voxels, 0.7)])
+    mu = np.array([[mu1], [mu2]])
+    d = np.stack([rng.poisson(1e4 * np.exp(-H @ (mu1 * c_true[0] + mu2 * c_true[1]))).astype(float),
+                  np.zeros(g.n_rays)])
+    Z = np.array([2 * mu1 * g.box_diagonal(), 2 * mu2 * g.box_diagonal()])
+    c0 = np.stack([np.full(g.n_voxels, 1.0), np.full(g.n_voxels, 0.2)])
     c_orc, _ = orc.iterate(g, I0, mu, d, None, Z, c0, 3)
-    c = c0[0].copy()
+    c = c0.copy()
     for _ in range(3):
-        q = 1e4 * np.exp(-mu0 * (H @ c))
+        q = 1e4 * np.exp(-H @ (mu1 * c[0] + mu2 * c[1]))
         bt, bh = H.T @ d[0], H.T @ q
         ok = (bt > 0) & (bh > 0)
-        c[ok] -= np.log(bt[ok] / bh[ok]) / Z[0]
-    assert np.allclose(c_orc[0], c, rtol=0, atol=1e-12)
-    assert np.array_equal(c_orc[1], c0[1])     # mu_2 = 0: no weight, no update
+        step = np.log(bt[ok] / bh[ok])
+        c[0, ok] -= step / Z[0]
+        c[1, ok] -= step / Z[1]
+    assert np.allclose(c_orc, c, rtol=0, atol=1e-12)
+    assert np.abs(c_orc - c0).max() > 1e-3
 
 
 def test_gradient_matches_finite_differences(orc):

@@ -82,7 +82,15 @@ def test_row_sum_is_box_chord(orc, name):
     assert np.abs(l - ref).max() < 1e-10
 
 
-@pytest.mark.parametrize("name,cx,cy,R", [("fan128", 17.3, -9.1, 21.0), ("fan64", -5.0, 8.0, 9.5)])
+def offset_fan():
+    """Anisotropic pixels, a channel offset and a start angle (all conventions exercised)."""
+    return G.Geometry(kind=0, nx=40, ny=30, nz=1, dx=1.2, dy=0.8, dz=1.0, n_views=30, n_rows=1,
+                      n_cols=64, sid=200.0, sdd=380.0, dgamma=G.fan_dgamma(40, 30, 1.2, 0.8, 200.0, 64) * 1.1,
+                      col_offset=0.37, drow_iso=1.0, beta0=0.41, views_per_rot=30.0, feed_per_rot=0.0)
+
+
+@pytest.mark.parametrize("name,cx,cy,R", [("fan128", 17.3, -9.1, 21.0), ("fan64", -5.0, 8.0, 9.5),
+                                          ("offset", 6.1, -3.3, 7.0)])
 def test_pixelised_disk_chord_bracket(orc, name, cx, cy, R):
     """T3: the pixelised disk (pixel on iff its centre is inside) lies between
     the disks of radius R-a and R+a, a = half pixel diagonal, so its projection
@@ -90,7 +98,7 @@ def test_pixelised_disk_chord_bracket(orc, name, cx, cy, R):
     the workload geometry (an independent numpy implementation), which also
     pins the source/detector conventions."""
     from workloads import geometry_for
-    g = geometry_for(name)
+    g = offset_fan() if name == "offset" else geometry_for(name)
     x = (np.arange(g.nx) + 0.5) * g.dx - g.nx * g.dx / 2
     y = (np.arange(g.ny) + 0.5) * g.dy - g.ny * g.dy / 2
     img = (((x[None, :] - cx) ** 2 + (y[:, None] - cy) ** 2) <= R * R).astype(np.float64)

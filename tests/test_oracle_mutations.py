@@ -1,0 +1,94 @@
+"""The pins catch plausible mistakes: each case plants one mistake in a copy of
+the oracle source (on the CPU), builds it, and requires that at least one pin
+fails when the oracle calls are routed to the mutant."""
+import os
+import shutil
+import tempfile
+
+import numpy as np
+import pytest
+
+import tests.test_oracle_deam as D
+import tests.test_oracle_geometry as Gm
+
+ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                          "oracle", "deam_oracle.c")
+
+MUTATIONS = {
+    "update_sign": ("c[(long)i * V + x] -= log(bt / bh) / Z[i];",
+                    "c[(long)i * V + x] += log(bt / bh) / Z[i];"),
+    "update_wrong_Z": ("c[(long)i * V + x] -= log(bt / bh) / Z[i];",
+                       "c[(long)i * V + x] -= log(bt / bh) / Z[0];"),
+    "no_substitution": ("if (metal) ra[i][j] = a[i][j];", "if (0) ra[i][j] = a[i][j];"),
+    "midpoint_rule": ("double am = 0.5 * (a0 + a1);", "double am = a0;"),
+    "exponent_sign": ("double ex = exp(-(mu1 * l1 + mu2 * l2));",
+                      "double ex = exp(-(mu1 * l1 - mu2 * l2));"),
+    "basis_swap": ("nadd(&as[1][j], mu2 * q);", "nadd(&as[1][j], mu1 * q);"),
+    "dropped_spectrum": ("for (int j = 0; j < 2; ++j) {\n        double q = I0[j * nE + e] * ex;",
+                         "for (int j = 0; j < 2; ++j) {\n        double q = I0[0 * nE + e] * ex;"),
+    "channel_offset_sign": ("- 0.5 * (g->n_cols - 1) - g->col_offset) * g->dgamma;",
+                            "- 0.5 * (g->n_cols - 1) + g->col_offset) * g->dgamma;"),
+    "fan_direction": ("double dirx = cg * ux - sg * uy, diry = sg * ux + cg * uy;",
+                      "double dirx = cg * ux + sg * uy, diry = -sg * ux + cg * uy;"),
+    "helix_direction": ("zs = ((double)v - 0.5 * (g->n_views - 1)) * g->feed_per_rot / g->views_per_rot;",
+                        "zs = (0.5 * (g->n_views - 1) - (double)v) * g->feed_per_rot / g->views_per_rot;"),
+    "idiv_term": ("term += (dj > 0.0 ? dj * log(dj / g) : 0.0) - dj + g;",
+                  "term += (dj > 0.0 ? dj * log(dj / g) : 0.0) + dj - g;"),
+    "band_overlap": ("int hi[3] = {g->nx, (b + 1) * band < g->ny ? (b + 1) * band : g->ny,",
+                     "int hi[3] = {g->nx, (b + 1) * band < g->ny ? (b + 1) * band + 1 : g->ny,"),
+    "grad_weight_sign": ("w[(long)i * R + y] = (ra[i][0] - a[i][0]) + (ra[i][1] - a[i][1]);",
+                         "w[(long)i * R + y] = (ra[i][0] - a[i][0]) - (ra[i][1] - a[i][1]);"),
+    "ray_length_2d": ("double L = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);",
+                      "double L = sqrt(D[0] * D[0] + D[1] * D[1]);"),
+}
+
+PINS = [
+    lambda o: Gm.test_siddon_matches_voxelwise_clipping(o, Gm.small_fan),
+    lambda o: Gm.test_siddon_matches_voxelwise_clipping(o, Gm.small_box3d),
+    lambda o: Gm.test_row_sum_is_box_chord(o, "fan64"),
+    lambda o: Gm.test_row_sum_is_box_chord(o, "helical_small"),
+    lambda o: Gm.test_pixelised_disk_chord_bracket(o, "fan64", -5.0, 8.0, 9.5),
+    lambda o: Gm.test_pixelised_disk_chord_bracket(o, "offset", 6.1, -3.3, 7.0),
+    lambda o: Gm.test_helical_cylinder_chord_bracket(o),
+    lambda o: Gm.test_adjoint_identity(o, "fan64"),
+    lambda o: D.test_single_bin_beer_lambert(o),
+    lambda o: D.test_flat_attenuation_sums_spectrum(o),
+    lambda o: D.test_linear_family_constraint(o),
+    lambda o: D.test_idiv_vanishes_on_consistent_data_and_matches_nll(o),
+    lambda o: D.test_all_metal_mask_is_noop(o),
+    lambda o: D.test_monoenergetic_matches_textbook_am(o),
+    lambda o: D.test_masked_idiv_nonincreasing(o, "fan64", 20, True),
+    lambda o: D.test_gradient_matches_finite_differences(o),
+]
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    d = tempfile.mkdtemp(prefix="orc_mut_")
+    yield d
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def test_pins_pass_on_the_real_oracle(orc):
+    for pin in PINS:
+        pin(orc)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(orc, workdir, name):
+    old, new = MUTATIONS[name]
+    src = open(ORACLE_SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    path = os.path.join(workdir, f"{name}.c")
+    open(path, "w").write(src.replace(old, new))
+    lib = orc.compile_library(path, os.path.join(workdir, f"lib{name}.so"))
+    caught = None
+    with orc.use_library(lib):
+        for i, pin in enumerate(PINS):
+            try:
+                with np.errstate(all="ignore"):
+                    pin(orc)
+            except (AssertionError, RuntimeError, ValueError, FloatingPointError):
+                caught = i
+                break
+    assert caught is not None, f"no pin caught the mutation {name}"

@@ -118,11 +118,18 @@ def expected_counts(geom, phantom, I0, threads=None):
     out = np.empty((2, geom.n_rays))
 
     def work(views):
+        # plain ufunc sums (no BLAS): safe to run from several threads and
+        # bitwise identical on every host
         S, P = G.ray_endpoints(geom, views)
-        A = lengths(S, P) @ mu_k               # (n, nE) line integrals per energy
-        g = np.exp(-A) @ I0_k.T                # (n, 2)
+        Lm = lengths(S, P)                      # (n, n_materials) path lengths
+        A = np.zeros((Lm.shape[0], mu_k.shape[1]))
+        for m in range(Lm.shape[1]):
+            A += Lm[:, m:m + 1] * mu_k[m][None, :]   # line integral per energy
+        np.negative(A, out=A)
+        np.exp(A, out=A)
         a = views[0] * geom.n_rows * geom.n_cols
-        out[:, a:a + g.shape[0]] = g.T
+        for j in range(2):
+            out[j, a:a + A.shape[0]] = (A * I0_k[j][None, :]).sum(axis=1)
 
     threads = threads or min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(threads) as ex:

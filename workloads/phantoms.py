@@ -110,12 +110,13 @@ class Cylinder:
         a = np.asarray(self.axis, dtype=np.float64)
         a = a / np.linalg.norm(a)
         w = S - c
-        wa, da = w @ a, D @ a
+        wa = w[:, 0] * a[0] + w[:, 1] * a[1] + w[:, 2] * a[2]
+        da = D[:, 0] * a[0] + D[:, 1] * a[1] + D[:, 2] * a[2]
         q0 = w - wa[:, None] * a
         q1 = D - da[:, None] * a
-        A = np.einsum("ij,ij->i", q1, q1)
-        B = 2.0 * np.einsum("ij,ij->i", q0, q1)
-        C = np.einsum("ij,ij->i", q0, q0) - self.radius ** 2
+        A = (q1 * q1).sum(axis=1)
+        B = 2.0 * (q0 * q1).sum(axis=1)
+        C = (q0 * q0).sum(axis=1) - self.radius ** 2
         lo, hi = _quad_interval(A, B, C)
         zl, zh = _slab_interval(wa, da, -self.half_length, self.half_length)
         lo, hi = np.maximum(np.maximum(lo, zl), 0.0), np.minimum(np.minimum(hi, zh), 1.0)
@@ -126,8 +127,8 @@ class Cylinder:
         a = np.asarray(self.axis, dtype=np.float64)
         a = a / np.linalg.norm(a)
         w = X - c
-        t = w @ a
-        r2 = np.einsum("...i,...i->...", w, w) - t * t
+        t = w[..., 0] * a[0] + w[..., 1] * a[1] + w[..., 2] * a[2]
+        r2 = (w * w).sum(axis=-1) - t * t
         return (r2 <= self.radius ** 2) & (np.abs(t) <= self.half_length)
 
     def bbox(self):
@@ -197,8 +198,8 @@ class BlobPhantom:
         out += box[:, None] * self.base[None, :]
         for k in range(len(self.sigma)):
             w = self.centers[k][None, :] - S[:, :2]
-            t = np.einsum("ij,ij->i", w, e)
-            d2 = np.einsum("ij,ij->i", w, w) - t * t
+            t = (w * e).sum(axis=1)
+            d2 = (w * w).sum(axis=1) - t * t
             s = self.sigma[k]
             # full-line integral; the ray end points lie far outside every blob
             li = s * math.sqrt(2.0 * math.pi) * np.exp(-np.maximum(d2, 0.0) / (2.0 * s * s))
