@@ -52,18 +52,20 @@ int check_plan(const deam_plan* p) {
 }
 
 // Tile of the backprojector for `bpv` bytes of accumulators per voxel:
-// tz = min(nz, 64) slices and as many columns as fit in 64 KiB of LDS
-// (capped at 16 x 16).
+// tz = min(nz, 64) slices and as many columns as fit in 80 KiB of LDS with
+// rows padded to tx + 1 words (capped at 16 x 16).
 deam::Tiling choose_tiling(const deam_geometry& g, int bpv) {
   deam::Tiling t{};
   const int nz = g.kind == DEAM_HELICAL3D ? g.nz : 1;
   t.tz = std::min(nz, 64);
-  int cols = std::max(1, 65536 / (t.tz * bpv));
+  const int budget = 81920 / (t.tz * bpv);   // padded columns that fit in 80 KiB (two tiles per CU)
   int tx = 1, ty = 1;
-  while (tx * ty * 2 <= cols && (tx < 16 || ty < 16)) {
-    if (tx <= ty && tx < 16) tx *= 2;
-    else if (ty < 16) ty *= 2;
-    else tx *= 2;
+  while ((tx < 16 || ty < 16)) {
+    const int ntx = (tx <= ty && tx < 16) ? tx * 2 : tx;
+    const int nty = (ntx == tx) ? ty * 2 : ty;
+    if ((ntx + 1) * nty > budget) break;
+    tx = ntx;
+    ty = nty;
   }
   t.tx = tx;
   t.ty = ty;
@@ -216,6 +218,13 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   if (n_energy <= 0 || n_energy > 100000) return fail(DEAM_ERR_SHAPE, "n_energy out of range");
   if (precision != DEAM_PREC_MIXED && precision != DEAM_PREC_FP64)
     return fail(DEAM_ERR_VALUE, "unknown precision %d", precision);
+  {
+    // the projector addresses both packed image copies with 32-bit byte offsets
+    const double V = (double)geom->nx * geom->ny * (geom->kind == DEAM_HELICAL3D ? geom->nz : 1);
+    const double bytes = 2.0 * V * 2.0 * (precision == DEAM_PREC_FP64 ? 8.0 : 4.0) + 512.0;
+    if (bytes >= 4294967296.0)
+      return fail(DEAM_ERR_UNSUPPORTED, "volume too large for this build (packed images >= 4 GiB)");
+  }
   for (int i = 0; i < 2 * n_energy; ++i) {
     if (!(std::isfinite(I0[i]) && I0[i] >= 0.0))
       return fail(DEAM_ERR_VALUE, "I0 must be finite and non-negative");
@@ -234,42 +243,94 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     return fail(DEAM_ERR_HIP, "hipGetDevice failed");
   }
 
-  // geometry tables (FP64)
-  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_cols * 2 + (size_t)g.n_rows);
+  // geometry tables (FP64): per view [cos b, sin b, z_s, w_s], per row [zeta_r/dz, L_r]
+  const double x0 = -0.5 * g.nx * g.dx, y0 = -0.5 * g.ny * g.dy;
+  const int nzv = is3d ? g.nz : 1;
+  const double z0 = -0.5 * nzv * g.dz;
+  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_rows * 2);
   double* tv = tab.data();
-  double* tc = tv + (size_t)g.n_views * 4;
-  double* tz = tc + (size_t)g.n_cols * 2;
+  double* tr = tv + (size_t)g.n_views * 4;
   for (int v = 0; v < g.n_views; ++v) {
     const double beta = g.beta0 + 2.0 * M_PI * (double)v / g.views_per_rot;
+    const double zs = is3d ? ((double)v - 0.5 * (g.n_views - 1)) * g.feed_per_rot / g.views_per_rot : 0.0;
     tv[4 * v] = std::cos(beta);
     tv[4 * v + 1] = std::sin(beta);
-    tv[4 * v + 2] = is3d ? ((double)v - 0.5 * (g.n_views - 1)) * g.feed_per_rot / g.views_per_rot : 0.0;
-    tv[4 * v + 3] = 0.0;
-  }
-  for (int k = 0; k < g.n_cols; ++k) {
-    const double gam = ((double)k - 0.5 * (g.n_cols - 1) - g.col_offset) * g.dgamma;
-    tc[2 * k] = std::cos(gam);
-    tc[2 * k + 1] = std::sin(gam);
+    tv[4 * v + 2] = zs;
+    tv[4 * v + 3] = (zs - z0) / g.dz;
   }
   const double dzeta = is3d ? g.drow_iso * g.sdd / g.sid : 1.0;
-  for (int r = 0; r < g.n_rows; ++r) tz[r] = is3d ? ((double)r - 0.5 * (g.n_rows - 1)) * dzeta : 0.0;
+  for (int r = 0; r < g.n_rows; ++r) {
+    const double zeta = is3d ? ((double)r - 0.5 * (g.n_rows - 1)) * dzeta : 0.0;
+    tr[2 * r] = zeta / g.dz;
+    tr[2 * r + 1] = std::sqrt(g.sdd * g.sdd + zeta * zeta);
+  }
+  // in-plane ray of every (view, channel), walked along its driving axis
+  const size_t nvk = (size_t)g.n_views * g.n_cols;
+  std::vector<deam::RayXY<double>> rays64(nvk);
+  std::vector<deam::RayXY<float>> rays32(precision == DEAM_PREC_MIXED ? nvk : 0);
+  for (int v = 0; v < g.n_views; ++v) {
+    const double cb = tv[4 * v], sb = tv[4 * v + 1];
+    for (int k = 0; k < g.n_cols; ++k) {
+      const double gam = ((double)k - 0.5 * (g.n_cols - 1) - g.col_offset) * g.dgamma;
+      const double cg = std::cos(gam), sg = std::sin(gam);
+      const double ex = -(cg * cb - sg * sb), ey = -(sg * cb + cg * sb);  // R(gamma) u
+      const double su = (g.sid * cb - x0) / g.dx, sv = (g.sid * sb - y0) / g.dy;
+      const double du = g.sdd * ex / g.dx, dv = g.sdd * ey / g.dy;
+      const bool yd = std::fabs(dv) >= std::fabs(du);
+      const double sa = yd ? sv : su, da = yd ? dv : du;
+      const double sbb = yd ? su : sv, db = yd ? du : dv;
+      const double mb = db / da;
+      deam::RayXY<double> t;
+      t.b0 = sbb - sa * mb;
+      t.mb = mb;
+      t.imb = mb != 0.0 ? 1.0 / mb : 1e30;
+      t.sa = sa;
+      t.ida = 1.0 / da;
+      t.iadb = db != 0.0 ? 1.0 / std::fabs(db) : 1e30;
+      t.yd = yd ? 1.0 : 0.0;
+      t.pad = 0.0;
+      const size_t i = (size_t)v * g.n_cols + k;
+      rays64[i] = t;
+      if (!rays32.empty()) {
+        deam::RayXY<float>& f = rays32[i];
+        f.b0 = (float)t.b0;
+        f.mb = (float)t.mb;
+        f.imb = (float)t.imb;
+        f.sa = (float)t.sa;
+        f.ida = (float)t.ida;
+        f.iadb = (float)t.iadb;
+        f.yd = (float)t.yd;
+        f.pad = 0.f;
+      }
+    }
+  }
 
   std::vector<unsigned char> etab;
   if (precision == DEAM_PREC_FP64) fill_energy<double>(etab, p->nE, n_energy, I0, mu);
   else fill_energy<float>(etab, p->nE, n_energy, I0, mu);
 
-  if (hipMalloc(&p->d_tables, tab.size() * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->d_energy, etab.size()) != hipSuccess) {
+  auto release = [&]() {
     if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_energy) (void)hipFree(p->d_energy);
+    if (p->d_rays) (void)hipFree(p->d_rays);
+    if (p->d_rays64) (void)hipFree(p->d_rays64);
     delete p;
+  };
+  if (hipMalloc(&p->d_tables, tab.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_energy, etab.size()) != hipSuccess ||
+      hipMalloc(&p->d_rays64, nvk * sizeof(deam::RayXY<double>)) != hipSuccess ||
+      (!rays32.empty() && hipMalloc(&p->d_rays, nvk * sizeof(deam::RayXY<float>)) != hipSuccess)) {
+    release();
     return fail(DEAM_ERR_HIP, "hipMalloc of plan tables failed");
   }
   if (hipMemcpy(p->d_tables, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(p->d_energy, etab.data(), etab.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(p->d_tables);
-    (void)hipFree(p->d_energy);
-    delete p;
+      hipMemcpy(p->d_energy, etab.data(), etab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_rays64, rays64.data(), nvk * sizeof(deam::RayXY<double>),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      (!rays32.empty() && hipMemcpy(p->d_rays, rays32.data(), nvk * sizeof(deam::RayXY<float>),
+                                    hipMemcpyHostToDevice) != hipSuccess)) {
+    release();
     return fail(DEAM_ERR_HIP, "hipMemcpy of plan tables failed");
   }
 
@@ -284,12 +345,9 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.dx = g.dx;
   G.dy = g.dy;
   G.dz = g.dz;
-  G.inv_dx = 1.0 / g.dx;
-  G.inv_dy = 1.0 / g.dy;
-  G.inv_dz = 1.0 / g.dz;
-  G.x0 = -0.5 * g.nx * g.dx;
-  G.y0 = -0.5 * g.ny * g.dy;
-  G.z0 = -0.5 * G.nz * g.dz;
+  G.x0 = x0;
+  G.y0 = y0;
+  G.z0 = z0;
   G.sid = g.sid;
   G.sdd = g.sdd;
   G.dgamma = g.dgamma;
@@ -297,18 +355,15 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.dzeta = dzeta;
   G.rc = 0.5 * (g.n_rows - 1);
   G.view = (const double*)p->d_tables;
-  G.chan = G.view + (size_t)g.n_views * 4;
-  G.zeta = G.chan + (size_t)g.n_cols * 2;
+  G.row = G.view + (size_t)g.n_views * 4;
+  G.rays = precision == DEAM_PREC_MIXED ? p->d_rays : p->d_rays64;
+  G.rays64 = (const deam::RayXY<double>*)p->d_rays64;
   G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
   G.V = (int64_t)g.nx * g.ny * G.nz;
 
   p->h1_bound = h1_bound(g);
-  p->tile_packed = choose_tiling(g, 16);
-  const int rs8 = 8;
-  p->tile_i64[1] = choose_tiling(g, 1 * rs8);
-  p->tile_i64[2] = choose_tiling(g, 2 * rs8);
-  p->tile_i64[3] = choose_tiling(g, 3 * rs8);
-  p->tile_i64[4] = choose_tiling(g, 4 * rs8);
+  p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
+  for (int n = 1; n <= 4; ++n) p->tile[n] = choose_tiling(g, 8 * n);
   p->fp_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
   *out = p;
   return ok();
@@ -318,6 +373,8 @@ int deam_plan_destroy(deam_plan* plan) {
   if (!plan) return fail(DEAM_ERR_NULL, "plan is NULL");
   (void)hipFree(plan->d_tables);
   (void)hipFree(plan->d_energy);
+  if (plan->d_rays) (void)hipFree(plan->d_rays);
+  (void)hipFree(plan->d_rays64);
   delete plan;
   return ok();
 }
@@ -413,7 +470,7 @@ int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b
   uint32_t* wmax = (uint32_t*)((char*)ws + L.wmax);
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
   HIP_TRY(deam::launch_absmax(plan, w, n_ch, wmax, st));
-  HIP_TRY(deam::launch_backproject(plan, w, n_ch, deam::ACC_I64, wmax, b, st));
+  HIP_TRY(deam::launch_backproject(plan, w, n_ch, false, wmax, b, st));
   return ok();
 }
 
@@ -444,7 +501,6 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
   void* cpx = w + L.cp_x;
   uint32_t* wmax = (uint32_t*)(w + L.wmax);
   double* partial = (double*)(w + L.partial);
-  const int acc = plan->precision == DEAM_PREC_FP64 ? deam::ACC_I64 : deam::ACC_PACKED;
   // events: per iteration, before/after the ray kernel, before/after the
   // backprojection, after the update
   std::vector<hipEvent_t> ev;
@@ -480,7 +536,7 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
     STEP(mark(k, 1));
     if (obj_hist) STEP(deam::launch_reduce(partial, plan->fp_blocks, obj_hist + k, st));
     STEP(mark(k, 2));
-    STEP(deam::launch_backproject(plan, w + L.w, 4, acc, wmax, w + L.b, st));
+    STEP(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
     STEP(mark(k, 3));
     STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
     STEP(mark(k, 4));

@@ -10,19 +10,33 @@
 
 namespace deam {
 
-// Geometry as the kernels see it: scalars by value, per-view / per-channel /
-// per-row tables in device memory (FP64; the ray set-up is always FP64).
+// In-plane description of the ray of one (view, channel), in grid units
+// (voxel index coordinates).  The ray is walked along its driving axis a
+// (y if |dy| >= |dx| in grid units, else x) and its lateral coordinate is
+// b(a) = b0 + a*mb.  Computed once per plan in FP64, stored in the plan
+// precision; shared by all detector rows of a helical channel.
+template <typename T>
+struct RayXY {
+  T b0, mb, imb;  // lateral line and 1/mb (huge when mb == 0)
+  T sa, ida;      // driving coordinate of the source, 1/da (da = in-plane run in grid units)
+  T iadb;         // 1/|db| (huge when db == 0)
+  T yd;           // 1 when a = y (rows), 0 when a = x
+  T pad;
+};
+
+// Geometry as the kernels see it.
 struct GeomDev {
   int is3d;
   int nx, ny, nz;
   int n_views, n_rows, n_cols;
-  double dx, dy, dz, inv_dx, inv_dy, inv_dz;
+  double dx, dy, dz;
   double x0, y0, z0;            // grid corner (mm)
   double sid, sdd, dgamma, kc;  // kc = (n_cols-1)/2 + col_offset
   double dzeta, rc;             // row pitch at the detector (mm), (n_rows-1)/2
-  const double* view;           // [n_views][4]: cos b, sin b, z_s, unused
-  const double* chan;           // [n_cols][2]:  cos g, sin g
-  const double* zeta;           // [n_rows]
+  const double* view;           // [n_views][4]: cos b, sin b, z_s (mm), w_s (grid units)
+  const double* row;            // [n_rows][2]: zeta_r / dz (grid units), 3D ray length L_r (mm)
+  const void* rays;             // RayXY<T> [n_views][n_cols] in the plan precision
+  const RayXY<double>* rays64;  // FP64 copy (metal trace, FP64 plans)
   int64_t R, V;
 };
 
@@ -42,7 +56,6 @@ struct Tiling {
 };
 
 enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
-enum AccMode { ACC_PACKED = 0, ACC_I64 = 1 };
 
 constexpr int kFpBlock = 256;
 constexpr int kBpBlock = 256;
@@ -66,12 +79,14 @@ struct deam_plan {
   int precision;
   int device;
   deam::GeomDev gd;
-  int nE;                        // kept energy bins
-  void* d_tables;                // view/chan/zeta tables (FP64)
+  int nE;                        // kept energy bins (padded to a multiple of 8)
+  void* d_tables;                // view/row tables (FP64)
+  void* d_rays;                  // RayXY<float> (MIXED only)
+  void* d_rays64;                // RayXY<double>
   void* d_energy;                // EBin<float> or EBin<double> [nE]
   double h1_bound;               // upper bound of max_x sum_y h(x,y)
-  deam::Tiling tile_packed;      // BP tiling for 2 packed u64 per voxel
-  deam::Tiling tile_i64[5];      // BP tiling for n_ch int64 per voxel (index n_ch)
+  double hmax;                   // upper bound of one h(x,y): the voxel diagonal
+  deam::Tiling tile[5];          // BP tiling for n_ch int64 words per voxel (index n_ch)
   int64_t fp_blocks;             // blocks of the ray kernels
 };
 
@@ -93,7 +108,8 @@ hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const 
 hipError_t launch_reduce(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmax, hipStream_t st);
-hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, int acc,
+// nonneg: every weight is >= 0 (the AM weights), which allows a cheaper rounding
+hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
                               const uint32_t* wmax, void* b, hipStream_t st);
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
                          void* c_proj, void* cp_y, void* cp_x, hipStream_t st);

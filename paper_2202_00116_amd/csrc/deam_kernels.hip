@@ -15,10 +15,15 @@
 // Backprojection.  Floating-point atomics are slow on this part (both in LDS
 // and in L2), while LDS integer atomics run at full rate.  Each workgroup
 // owns a tile of voxels in LDS, loops over all views, walks every ray that
-// crosses its tile (clipped to the tile) and accumulates h*w in fixed point
-// with 64-bit integer LDS atomics.  Integer addition is associative, so the
-// result is bitwise reproducible, and the tile is written once with plain
-// stores: no global atomics, no partial images.
+// crosses its tile (clipped to the tile) and accumulates h*w in 64-bit
+// fixed point with integer LDS atomics.  Integer addition is associative,
+// so the result is bitwise reproducible, and the tile is written once with
+// plain stores: no global atomics, no partial images.
+//
+// Ray set-up.  The in-plane part of every (view, channel) ray is computed
+// once per plan in FP64 and stored in the plan precision (RayXY); the
+// forward projector and the backprojector both start from it, so their
+// segment lengths agree bit for bit away from tile edges.
 #include "deam_internal.hpp"
 
 #include <algorithm>
@@ -32,7 +37,11 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// max(lo, min(v, hi)) lowers to a single v_med3_i32
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return max(lo, min(v, hi)); }
+// floor and convert in one instruction
+__device__ __forceinline__ int ifloor(float x) { return __float2int_rd(x); }
+__device__ __forceinline__ int ifloor(double x) { return __double2int_rd(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 
@@ -55,112 +64,106 @@ struct Ray {
   int ydrive;     // 1: a = y (rows) and b = x; 0: a = x and b = y
 };
 
-// Ray (v, r, k) clipped to the box [lo, hi] (grid units, axes x, y, z).
+// Ray (v, r, k) clipped to the voxel box [lo, hi) (grid units, axes x, y, z).
+// Returns false if the ray misses the box.
 template <typename T>
-__device__ bool ray_setup(const GeomDev& G, int v, int r, int k, double lox, double loy,
-                          double loz, double hix, double hiy, double hiz, Ray<T>& ry) {
-  const double cb = G.view[4 * v], sb = G.view[4 * v + 1], zs = G.view[4 * v + 2];
-  const double cg = G.chan[2 * k], sg = G.chan[2 * k + 1];
-  const double ex = -(cg * cb - sg * sb), ey = -(sg * cb + cg * sb);  // R(gamma) u
-  const double Dz = G.is3d ? G.zeta[r] : 0.0;
-  const double su = (G.sid * cb - G.x0) * G.inv_dx;
-  const double sv = (G.sid * sb - G.y0) * G.inv_dy;
-  const double sw = (zs - G.z0) * G.inv_dz;
-  const double du = G.sdd * ex * G.inv_dx, dv = G.sdd * ey * G.inv_dy, dw = Dz * G.inv_dz;
-  const double L = sqrt(G.sdd * G.sdd + Dz * Dz);
-  const bool yd = fabs(dv) >= fabs(du);
-  const double sa = yd ? sv : su, da = yd ? dv : du;
-  const double sbb = yd ? su : sv, db = yd ? du : dv;
-  const double alo_box = yd ? loy : lox, ahi_box = yd ? hiy : hix;
-  const double blo_box = yd ? lox : loy, bhi_box = yd ? hix : hiy;
-  const double mb = db / da, mw = dw / da;
-  const double b0 = sbb - sa * mb, w0 = sw - sa * mw;
-  double alo = fmax(fmin(sa, sa + da), alo_box);
-  double ahi = fmin(fmax(sa, sa + da), ahi_box);
-  if (mb != 0.0) {
-    const double t0 = (blo_box - b0) / mb, t1 = (bhi_box - b0) / mb;
+__device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
+                                         int v, int r, int k, int lox, int loy, int loz, int hix,
+                                         int hiy, int hiz, Ray<T>& ry) {
+  const RayXY<T> t = rays[(int64_t)v * G.n_cols + k];
+  const bool yd = t.yd != (T)0;
+  const T Lr = (T)G.row[2 * r + 1];
+  T mw = 0, w0 = (T)0.5, imw = 0;
+  if (G.is3d) {
+    mw = (T)G.row[2 * r] * t.ida;
+    w0 = (T)G.view[4 * v + 3] - t.sa * mw;
+    imw = mw != (T)0 ? (T)1 / fabs(mw) : (T)0;
+  }
+  const T alo_box = (T)(yd ? loy : lox), ahi_box = (T)(yd ? hiy : hix);
+  const T blo = (T)(yd ? lox : loy), bhi = (T)(yd ? hix : hiy);
+  T alo = alo_box, ahi = ahi_box;
+  if (t.mb != (T)0) {
+    const T t0 = (blo - t.b0) * t.imb, t1 = (bhi - t.b0) * t.imb;
     alo = fmax(alo, fmin(t0, t1));
     ahi = fmin(ahi, fmax(t0, t1));
-  } else if (!(b0 >= blo_box && b0 < bhi_box)) {
+  } else if (!(t.b0 >= blo && t.b0 < bhi)) {
     return false;
   }
   if (G.is3d) {
-    if (mw != 0.0) {
-      const double t0 = (loz - w0) / mw, t1 = (hiz - w0) / mw;
+    if (mw != (T)0) {
+      const T t0 = ((T)loz - w0) / mw, t1 = ((T)hiz - w0) / mw;
       alo = fmax(alo, fmin(t0, t1));
       ahi = fmin(ahi, fmax(t0, t1));
-    } else if (!(w0 >= loz && w0 < hiz)) {
+    } else if (!(w0 >= (T)loz && w0 < (T)hiz)) {
       return false;
     }
   }
   if (!(ahi > alo)) return false;
-  ry.b0 = (T)b0;
-  ry.mb = (T)mb;
-  ry.w0 = (T)w0;
-  ry.mw = (T)mw;
-  ry.imw = mw != 0.0 ? (T)(1.0 / fabs(mw)) : (T)0;
-  ry.La = (T)(L / fabs(da));
-  ry.Lb = db != 0.0 ? (T)(L / fabs(db)) : (T)FLT_MAX;
-  ry.alo = (T)alo;
-  ry.ahi = (T)ahi;
+  ry.b0 = t.b0;
+  ry.mb = t.mb;
+  ry.w0 = w0;
+  ry.mw = mw;
+  ry.imw = imw;
+  ry.La = Lr * fabs(t.ida);
+  ry.Lb = Lr * t.iadb;
+  ry.alo = alo;
+  ry.ahi = ahi;
   ry.ydrive = yd ? 1 : 0;
   return true;
 }
 
 // One piece [va, vb] of a plane step at axial index iw: split at the
 // lateral plane it crosses (at most one, since |mb| <= 1).
-template <typename T, typename F>
+template <typename T, bool SKIP, typename F>
 __device__ __forceinline__ void walk_piece(const Ray<T>& ry, int ia, T va, T vb, int iw, int blo,
                                            int bhi, F& visit) {
   const T ba = fma(va, ry.mb, ry.b0), bb = fma(vb, ry.mb, ry.b0);
-  const int A = clampi((int)floor(ba), blo, bhi - 1);
-  int B = clampi((int)floor(bb), blo, bhi - 1);
+  const int A = clampi(ifloor(ba), blo, bhi - 1);
+  int B = clampi(ifloor(bb), blo, bhi - 1);
   B = clampi(B, A - 1, A + 1);
   const T seg = (vb - va) * ry.La;
   T hA = seg;
   if (A != B) hA = fmin(fabs((T)(A > B ? A : B) - ba) * ry.Lb, seg);
   visit(ia, A, iw, hA);
-  visit(ia, B, iw, seg - hA);
+  if (!SKIP || B != A) visit(ia, B, iw, seg - hA);
 }
 
-// Walk the plane steps ia of the driving axis inside [alo, ahi], restricted
+// One plane step ia of the driving axis (clipped to [alo, ahi]), restricted
 // to lateral indices [blo, bhi) and axial indices [wlo, whi).  visit(ia, ib,
-// iw, h) receives every segment (h may be 0); flush() is called every 16
-// steps (used for compensated summation).
-template <typename T, bool Z3, typename F, typename G>
-__device__ __forceinline__ void walk(const Ray<T>& ry, int alo_i, int ahi_i, int blo, int bhi,
-                                     int wlo, int whi, F& visit, G& flush) {
-  const int ia0 = max((int)floor(ry.alo), alo_i);
-  const int ia1 = min((int)ceil(ry.ahi) - 1, ahi_i - 1);
-  int cnt = 0;
-  for (int ia = ia0; ia <= ia1; ++ia) {
-    const T va = fmax((T)ia, ry.alo), vb = fmin((T)(ia + 1), ry.ahi);
-    if (vb > va) {
-      if constexpr (Z3) {
-        const T wa = fma(va, ry.mw, ry.w0), wb = fma(vb, ry.mw, ry.w0);
-        int C = clampi((int)floor(wa), wlo, whi - 1);
-        const int D = clampi((int)floor(wb), wlo, whi - 1);
-        T vcur = va, wcur = wa;
-        while (C != D) {  // axial plane crossings inside this step (rare)
-          const int dir = D > C ? 1 : -1;
-          const T wz = (T)(dir > 0 ? C + 1 : C);
-          const T vz = fmin(fmax(vcur + fabs(wz - wcur) * ry.imw, vcur), vb);
-          walk_piece(ry, ia, vcur, vz, C, blo, bhi, visit);
-          vcur = vz;
-          wcur = wz;
-          C += dir;
-        }
-        walk_piece(ry, ia, vcur, vb, C, blo, bhi, visit);
-      } else {
-        walk_piece(ry, ia, va, vb, 0, blo, bhi, visit);
-      }
+// iw, h) receives every segment (with SKIP = false also a zero-length second
+// visit per piece, which keeps the loads of the forward projector uniform).
+template <typename T, bool Z3, bool SKIP, typename F>
+__device__ __forceinline__ void walk_row(const Ray<T>& ry, int ia, int blo, int bhi, int wlo,
+                                         int whi, F& visit) {
+  const T va = fmax((T)ia, ry.alo), vb = fmin((T)(ia + 1), ry.ahi);
+  if (!(vb > va)) return;
+  if constexpr (Z3) {
+    const T wa = fma(va, ry.mw, ry.w0), wb = fma(vb, ry.mw, ry.w0);
+    int C = clampi(ifloor(wa), wlo, whi - 1);
+    const int D = clampi(ifloor(wb), wlo, whi - 1);
+    T vcur = va, wcur = wa;
+    while (C != D) {  // axial plane crossings inside this step (rare)
+      const int dir = D > C ? 1 : -1;
+      const T wz = (T)(dir > 0 ? C + 1 : C);
+      const T vz = fmin(fmax(vcur + fabs(wz - wcur) * ry.imw, vcur), vb);
+      walk_piece<T, SKIP>(ry, ia, vcur, vz, C, blo, bhi, visit);
+      vcur = vz;
+      wcur = wz;
+      C += dir;
     }
-    if (++cnt == 16) {
-      flush();
-      cnt = 0;
-    }
+    walk_piece<T, SKIP>(ry, ia, vcur, vb, C, blo, bhi, visit);
+  } else {
+    walk_piece<T, SKIP>(ry, ia, va, vb, 0, blo, bhi, visit);
   }
-  flush();
+}
+
+// All plane steps of the ray inside [alo_i, ahi_i) (driving-axis indices).
+template <typename T, bool Z3, bool SKIP, typename F>
+__device__ __forceinline__ void walk(const Ray<T>& ry, int alo_i, int ahi_i, int blo, int bhi,
+                                     int wlo, int whi, F& visit) {
+  const int ia0 = max(ifloor(ry.alo), alo_i);
+  const int ia1 = min((int)ceil(ry.ahi) - 1, ahi_i - 1);
+  for (int ia = ia0; ia <= ia1; ++ia) walk_row<T, Z3, SKIP>(ry, ia, blo, bhi, wlo, whi, visit);
 }
 
 template <typename T>
@@ -171,23 +174,30 @@ __device__ __forceinline__ void neumaier(T& s, T& c, T x) {
 }
 
 // Line integrals of the two packed components along one ray (compensated).
+// cp holds the packed image twice: natural order at element 0 and x-major at
+// element xoff; rays driven along y read the first copy, rays driven along
+// x the second, so neighbouring lanes gather neighbouring addresses.
+// Plane steps fully inside the ray's range (va = ia, vb = ia + 1) in the same
+// slice are processed four at a time with all gathers issued before the
+// accumulation; partial end steps and steps with an axial crossing go
+// through walk_row (the arithmetic of both paths is identical).
 template <typename T, bool Z3>
-__device__ void project_ray(const GeomDev& G, const typename Vec2<T>::type* __restrict__ cpy,
-                            const typename Vec2<T>::type* __restrict__ cpx, int v, int r, int k,
-                            T& l1, T& l2) {
+__device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
+                            const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff, int v,
+                            int r, int k, T& l1, T& l2) {
+  using T2 = typename Vec2<T>::type;
   l1 = 0;
   l2 = 0;
   Ray<T> ry;
-  if (!ray_setup<T>(G, v, r, k, 0.0, 0.0, 0.0, (double)G.nx, (double)G.ny,
-                    (double)(G.is3d ? G.nz : 1), ry))
-    return;
-  const typename Vec2<T>::type* __restrict__ base = ry.ydrive ? cpy : cpx;
-  const uint32_t nb = ry.ydrive ? G.nx : G.ny;
-  const uint32_t na = ry.ydrive ? G.ny : G.nx;
+  const int nzz = G.is3d ? G.nz : 1;
+  if (!make_ray<T>(G, rays, v, r, k, 0, 0, 0, G.nx, G.ny, nzz, ry)) return;
+  const uint32_t base = ry.ydrive ? 0u : xoff;
+  const int nb = ry.ydrive ? G.nx : G.ny;
+  const int na = ry.ydrive ? G.ny : G.nx;
   const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
   T s1 = 0, c1 = 0, s2 = 0, c2 = 0, p1 = 0, p2 = 0;
   auto visit = [&](int ia, int ib, int iw, T h) {
-    const auto cv = base[(uint32_t)iw * plane + (uint32_t)ia * nb + (uint32_t)ib];
+    const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
     p1 = fma(h, cv.x, p1);
     p2 = fma(h, cv.y, p2);
   };
@@ -197,7 +207,76 @@ __device__ void project_ray(const GeomDev& G, const typename Vec2<T>::type* __re
     p1 = 0;
     p2 = 0;
   };
-  walk<T, Z3>(ry, 0, (int)na, 0, (int)nb, 0, G.is3d ? G.nz : 1, visit, flush);
+  const int ia0 = max(ifloor(ry.alo), 0);
+  const int ia1 = min((int)ceil(ry.ahi) - 1, na - 1);
+  const int fa = max((int)ceil(ry.alo), ia0);            // first full step
+  const int fb = min(ifloor(ry.ahi) - 1, ia1);       // last full step
+  int ia = ia0;
+  for (; ia < fa && ia <= ia1; ++ia) walk_row<T, Z3, false>(ry, ia, 0, nb, 0, nzz, visit);
+  const T La = ry.La;
+  int groups = 0;
+  for (; ia + 3 <= fb; ia += 4) {
+    T bq[5];
+    int F[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      bq[q] = fma((T)(ia + q), ry.mb, ry.b0);
+      F[q] = clampi(ifloor(bq[q]), 0, nb - 1);
+    }
+    int iw = 0;
+    if constexpr (Z3) {
+      const int G0 = clampi(ifloor(fma((T)ia, ry.mw, ry.w0)), 0, nzz - 1);
+      const int G4 = clampi(ifloor(fma((T)(ia + 4), ry.mw, ry.w0)), 0, nzz - 1);
+      if (G0 != G4) {
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) walk_row<T, Z3, false>(ry, ia + q, 0, nb, 0, nzz, visit);
+        if (++groups == 4) {
+          flush();
+          groups = 0;
+        }
+        continue;
+      }
+      iw = G0;
+    }
+    // 32-bit byte offsets from the uniform base (the packed images are far
+    // below 4 GiB; the plan checks it)
+    uint32_t oA[4], oB[4];
+    T hA[4], hB[4];
+    const uint32_t row0 =
+        (base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb) * (uint32_t)sizeof(T2);
+    const uint32_t rstep = (uint32_t)nb * (uint32_t)sizeof(T2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int A = F[q];
+      const int B = clampi(F[q + 1], A - 1, A + 1);
+      const T split = fmin(fabs((T)max(A, B) - bq[q]) * ry.Lb, La);
+      hA[q] = (A == B) ? La : split;
+      hB[q] = La - hA[q];
+      const uint32_t rq = row0 + (uint32_t)q * rstep;
+      oA[q] = rq + (uint32_t)A * (uint32_t)sizeof(T2);
+      oB[q] = rq + (uint32_t)B * (uint32_t)sizeof(T2);
+    }
+    T2 vA[4], vB[4];
+    const char* __restrict__ cpb = (const char*)cp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      vA[q] = *(const T2*)(cpb + oA[q]);
+      vB[q] = *(const T2*)(cpb + oB[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      p1 = fma(hA[q], vA[q].x, p1);
+      p2 = fma(hA[q], vA[q].y, p2);
+      p1 = fma(hB[q], vB[q].x, p1);
+      p2 = fma(hB[q], vB[q].y, p2);
+    }
+    if (++groups == 4) {
+      flush();
+      groups = 0;
+    }
+  }
+  for (; ia <= ia1; ++ia) walk_row<T, Z3, false>(ry, ia, 0, nb, 0, nzz, visit);
+  flush();
   l1 = s1 + c1;
   l2 = s2 + c2;
 }
@@ -342,8 +421,8 @@ __device__ void block_reduce(double term, const float wabs[4], int nch, double* 
 // ---------------------------------------------------------------------------
 template <typename T, bool Z3, int MODE>
 __global__ __launch_bounds__(kFpBlock) void k_fp(
-    GeomDev G, const typename Vec2<T>::type* __restrict__ cpy,
-    const typename Vec2<T>::type* __restrict__ cpx, const EBin<T>* __restrict__ eb, int nE,
+    GeomDev G, const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff,
+    const EBin<T>* __restrict__ eb, int nE,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
     double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
     uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
@@ -357,7 +436,8 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
     const int rv = (int)(ray / G.n_cols);
     const int r = rv % G.n_rows, v = rv / G.n_rows;
     T l1, l2;
-    project_ray<T, Z3>(G, cpy, cpx, v, r, k, l1, l2);
+    const RayXY<T>* rays = (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
+    project_ray<T, Z3>(G, rays, cp, xoff, v, r, k, l1, l2);
     if constexpr (MODE == PM_L) {
       out[ray] = l1;
       if (nout > 1) out[G.R + ray] = l2;
@@ -424,36 +504,71 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ p, i
 // ---------------------------------------------------------------------------
 // Backprojection: tile-owned, fixed point in LDS
 // ---------------------------------------------------------------------------
-// Fixed-point formats:
-//   ACC_PACKED: 4 non-negative channels as two 64-bit words, each holding two
-//     unsigned 32-bit fields; scale_c = 2^31 / (h1 * max w_c), so no field
-//     can exceed 2^31 + (number of additions)/2 < 2^32 and no carry crosses
-//     fields.  Contributions are rounded half up.
-//   ACC_I64: one signed 64-bit word per channel, scale_c = 2^61 / (h1 * max|w_c|).
-// h1 is an upper bound of max_x sum_y h(x,y) computed from the geometry.
-template <typename T, bool Z3, int ACC, int NCH>
+// Fixed point: one signed 64-bit word per voxel and channel holding the sum
+// of round(h * w_c * s_c).
+//  * FP32 plans: s_c = (2^31 - 2^8) / (hmax * max|w_c|), hmax = the voxel
+//    diagonal (no segment is longer), so every term fits a signed 32-bit
+//    integer and converts with one instruction; the resolution is 2^-31 of
+//    the largest possible term, below the FP32 rounding of the product for
+//    all but terms 2^8 times smaller than the largest, and sums of up to 2^32
+//    terms cannot overflow 64 bits.
+//  * FP64 plans: s_c = 2^61 / (h1 * max|w_c|), h1 >= max_x sum_y h(x,y), so
+//    every partial sum stays below 2^61 + (number of additions)/2 < 2^63; a
+//    term (< 2^52) is split exactly into two 32-bit halves.
+// Integer sums are exact, so the result does not depend on the order of the
+// additions.
+__device__ __forceinline__ unsigned long long to_fixed(float x) {
+  const int q = (int)rintf(x);          // |x| < 2^31 by the choice of the scale
+  return (unsigned long long)(long long)q;
+}
+
+// Non-negative terms (the AM weights): round half up with one FMA.
+__device__ __forceinline__ unsigned long long to_fixed_nonneg(float h, float ws) {
+  return (unsigned long long)(uint32_t)fmaf(h, ws, 0.5f);
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(double x) {
+  const double ax = fabs(x) + 0.5;                        // round half away from zero
+  const double hi = floor(ax * 2.3283064365386963e-10);   // 2^-32, exact scaling
+  const double lo = fma(-hi, 4294967296.0, ax);           // ax - hi*2^32, exact
+  unsigned long long q = ((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo;
+  return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
+}
+
+template <typename T, bool Z3, int NCH, bool NONNEG>
 __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
-                                                 T* __restrict__ b) {
+                                                 double hmax, T* __restrict__ b) {
   extern __shared__ unsigned long long acc[];
-  constexpr int WPV = (ACC == ACC_PACKED) ? NCH / 2 : NCH;  // 64-bit words per voxel
   __shared__ float s_kap[kViewBatch][4];
-  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_off[kViewBatch + 1];
+  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_nr[kViewBatch];
+  __shared__ int s_off[kViewBatch + 1];
+  const RayXY<T>* __restrict__ rays =
+      (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
 
-  const int t = blockIdx.x;
+  // tiles in row-major order; each XCD gets a contiguous band of them, so the
+  // rays a tile reads are mostly read by other tiles of the same L2
+  const int t = xcd_block(blockIdx.x, gridDim.x);
   const int tix = t % TL.ntx, tiy = (t / TL.ntx) % TL.nty, tiz = t / (TL.ntx * TL.nty);
   const int tx0 = tix * TL.tx, ty0 = tiy * TL.ty, tz0 = tiz * TL.tz;
   const int tx1 = min(tx0 + TL.tx, G.nx), ty1 = min(ty0 + TL.ty, G.ny);
   const int tz1 = min(tz0 + TL.tz, G.is3d ? G.nz : 1);
-  const int nvox = TL.tx * TL.ty * TL.tz;
-  for (int i = threadIdx.x; i < nvox * WPV; i += kBpBlock) acc[i] = 0ull;
+  // LDS layout: acc[c][z][y][x] with a row stride of tx + 1 words, so that
+  // lanes walking neighbouring rays of one view (neighbouring x for rays
+  // driven along y, neighbouring y for rays driven along x) hit distinct banks
+  const int rs = TL.tx + 1;
+  const int txy = rs * TL.ty;
+  const int nvox = txy * TL.tz;
+  for (int i = threadIdx.x; i < nvox * NCH; i += kBpBlock) acc[i] = 0ull;
 
   double scale[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const float m = __uint_as_float(wmax[c]);
-    const double top = (ACC == ACC_PACKED) ? 2147483648.0 : 2305843009213693952.0;
-    scale[c] = (m > 0.f && h1 > 0.0) ? top / (h1 * (double)m) : 0.0;
+    if (sizeof(T) == 4)
+      scale[c] = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
+    else
+      scale[c] = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
   }
 
   // tile rectangle (mm) and axial range
@@ -488,6 +603,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
         const int kh = min((int)floorf(kmx + 0.01f), G.n_cols - 1);
         nk = max(kh - kl + 1, 0);
         if (G.is3d) {
+          // detector rows whose rays can meet the tile's slices
           const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
           const double zs = G.view[4 * v + 2];
           const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
@@ -498,92 +614,76 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
           const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
           const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
           rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
-          const int rh = min((int)floor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
+          const int rh = min(ifloor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
           nr = max(rh - rl + 1, 0);
         } else {
           nr = 1;
         }
       }
       s_kl[j] = kl;
-      s_nk[j] = nk;
+      s_nk[j] = nr > 0 ? nk : 0;
       s_rl[j] = rl;
-      s_off[j] = nk * nr;
+      s_nr[j] = nr;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int run = 0;
       for (int j = 0; j < kViewBatch; ++j) {
-        const int n = s_off[j];
         s_off[j] = run;
-        run += n;
+        run += s_nk[j];
       }
       s_off[kViewBatch] = run;
     }
     __syncthreads();
     const int total = s_off[kViewBatch];
+    // one item per (view, channel); the thread walks all of its detector rows
     for (int it = threadIdx.x; it < total; it += kBpBlock) {
       int j = 0;
 #pragma unroll
       for (int q = 1; q < kViewBatch; ++q) j += (it >= s_off[q]) ? 1 : 0;
-      const int loc = it - s_off[j];
-      const int nk = s_nk[j];
-      const int r = s_rl[j] + loc / nk, k = s_kl[j] + loc % nk;
+      const int k = s_kl[j] + (it - s_off[j]);
       const int v = vb0 + j;
-      Ray<T> ry;
-      if (!ray_setup<T>(G, v, r, k, (double)tx0, (double)ty0, (double)tz0, (double)tx1,
-                        (double)ty1, (double)tz1, ry))
-        continue;
-      const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
-      T ws[NCH];
-      double wsd[NCH];
+      const int r0 = s_rl[j], r1 = r0 + s_nr[j];
+      for (int r = r0; r < r1; ++r) {
+        Ray<T> ry;
+        if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
+        const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
+        T ws[NCH];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        wsd[c] = (double)w[c * G.R + ray] * scale[c];
-        ws[c] = (T)wsd[c];
-      }
-      const int la = ry.ydrive ? ty0 : tx0, ha = ry.ydrive ? ty1 : tx1;
-      const int lbb = ry.ydrive ? tx0 : ty0, hb = ry.ydrive ? tx1 : ty1;
-      const int sa = ry.ydrive ? TL.tx : 1, sbs = ry.ydrive ? 1 : TL.tx;
-      const int txy = TL.tx * TL.ty;
-      auto visit = [&](int ia, int ib, int iw, T h) {
-        const int li = (iw - tz0) * txy + (ia - la) * sa + (ib - lbb) * sbs;
-        if constexpr (ACC == ACC_PACKED) {
-#pragma unroll
-          for (int q = 0; q < NCH / 2; ++q) {
-            const uint32_t f0 = (uint32_t)fma(h, ws[2 * q], (T)0.5);
-            const uint32_t f1 = (uint32_t)fma(h, ws[2 * q + 1], (T)0.5);
-            atomicAdd(&acc[li * WPV + q], ((unsigned long long)f1 << 32) | (unsigned long long)f0);
-          }
-        } else {
+        for (int c = 0; c < NCH; ++c) ws[c] = (T)((double)w[c * G.R + ray] * scale[c]);
+        const int la = ry.ydrive ? ty0 : tx0, ha = ry.ydrive ? ty1 : tx1;
+        const int lbb = ry.ydrive ? tx0 : ty0, hb = ry.ydrive ? tx1 : ty1;
+        const int sa = ry.ydrive ? rs : 1, sbs = ry.ydrive ? 1 : rs;
+        // accumulators are channel-major (acc[c][voxel]) so that lanes at
+        // neighbouring voxels hit neighbouring LDS banks
+        auto visit = [&](int ia, int ib, int iw, T h) {
+          const int li = (iw - tz0) * txy + (ia - la) * sa + (ib - lbb) * sbs;
 #pragma unroll
           for (int c = 0; c < NCH; ++c) {
-            const long long q = __double2ll_rn((double)h * wsd[c]);
-            atomicAdd(&acc[li * WPV + c], (unsigned long long)q);
+            if constexpr (NONNEG && sizeof(T) == 4)
+              atomicAdd(&acc[c * nvox + li], to_fixed_nonneg((float)h, (float)ws[c]));
+            else
+              atomicAdd(&acc[c * nvox + li], to_fixed(h * ws[c]));
           }
-        }
-      };
-      auto noflush = [&]() {};
-      walk<T, Z3>(ry, la, ha, lbb, hb, tz0, tz1, visit, noflush);
+        };
+        // every lane steps through all plane steps of the tile (steps outside
+        // its ray are empty), so at each step the lanes of a wave touch
+        // neighbouring accumulators
+        for (int ia = la; ia < ha; ++ia) walk_row<T, Z3, true>(ry, ia, lbb, hb, tz0, tz1, visit);
+      }
     }
     __syncthreads();
   }
 
   // write the tile
   for (int i = threadIdx.x; i < nvox; i += kBpBlock) {
-    const int lx = i % TL.tx, ly = (i / TL.tx) % TL.ty, lz = i / (TL.tx * TL.ty);
+    const int lx = i % rs, ly = (i / rs) % TL.ty, lz = i / txy;
     const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
-    if (gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
+    if (lx >= TL.tx || gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
     const int64_t gi = ((int64_t)gz * G.ny + gy) * G.nx + gx;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-      double val;
-      if constexpr (ACC == ACC_PACKED) {
-        const unsigned long long word = acc[i * WPV + c / 2];
-        const uint32_t f = (c & 1) ? (uint32_t)(word >> 32) : (uint32_t)(word & 0xffffffffull);
-        val = (double)f;
-      } else {
-        val = (double)(long long)acc[i * WPV + c];
-      }
+      const double val = (double)(long long)acc[c * nvox + i];
       b[c * G.V + gi] = scale[c] > 0.0 ? (T)(val / scale[c]) : (T)0;
     }
   }
@@ -698,14 +798,14 @@ static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, 
   using T2 = typename Vec2<T>::type;
   const dim3 grid((unsigned)p->fp_blocks), blk(kFpBlock);
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
+  // the x-major copy follows the natural one in the same allocation
+  const uint32_t xoff = (uint32_t)(((const T2*)cp_x) - ((const T2*)cp_y));
   if (p->gd.is3d)
-    hipLaunchKernelGGL((k_fp<T, true, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y,
-                       (const T2*)cp_x, eb, p->nE, d, mask, (T*)out, partial, wmax, tthr,
-                       mask_out, Tout, nout);
+    hipLaunchKernelGGL((k_fp<T, true, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
+                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
   else
-    hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y,
-                       (const T2*)cp_x, eb, p->nE, d, mask, (T*)out, partial, wmax, tthr,
-                       mask_out, Tout, nout);
+    hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
+                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
 }
 
 hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
@@ -793,46 +893,41 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
   return hipGetLastError();
 }
 
-template <typename T, bool Z3, int ACC, int NCH>
-static hipError_t bp_go(const deam_plan* p, const Tiling& TL, const void* w, const uint32_t* wmax,
-                        void* b, hipStream_t st) {
-  constexpr int WPV = (ACC == ACC_PACKED) ? NCH / 2 : NCH;
-  const size_t lds = (size_t)TL.tx * TL.ty * TL.tz * WPV * 8;
+template <typename T, bool Z3, int NCH, bool NONNEG>
+static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
+                        hipStream_t st) {
+  const Tiling& TL = p->tile[NCH];
+  const size_t lds = (size_t)(TL.tx + 1) * TL.ty * TL.tz * NCH * 8;
   const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
-  auto kern = k_bp<T, Z3, ACC, NCH>;
+  auto kern = k_bp<T, Z3, NCH, NONNEG>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nt), dim3(kBpBlock), lds, st, p->gd, TL, (const T*)w, wmax,
-                     p->h1_bound, (T*)b);
+                     p->h1_bound, p->hmax, (T*)b);
   return hipGetLastError();
 }
 
 template <typename T, bool Z3>
-static hipError_t bp_by_channels(const deam_plan* p, const void* w, int n_ch, int acc,
+static hipError_t bp_by_channels(const deam_plan* p, const void* w, int n_ch, bool nonneg,
                                  const uint32_t* wmax, void* b, hipStream_t st) {
-  if (acc == ACC_PACKED) {
-    if (n_ch != 4) return hipErrorInvalidValue;
-    return bp_go<T, Z3, ACC_PACKED, 4>(p, p->tile_packed, w, wmax, b, st);
-  }
   switch (n_ch) {
-    case 1: return bp_go<T, Z3, ACC_I64, 1>(p, p->tile_i64[1], w, wmax, b, st);
-    case 2: return bp_go<T, Z3, ACC_I64, 2>(p, p->tile_i64[2], w, wmax, b, st);
-    case 4: return bp_go<T, Z3, ACC_I64, 4>(p, p->tile_i64[4], w, wmax, b, st);
+    case 1: return bp_go<T, Z3, 1, false>(p, w, wmax, b, st);
+    case 2: return bp_go<T, Z3, 2, false>(p, w, wmax, b, st);
+    case 4:
+      return nonneg ? bp_go<T, Z3, 4, true>(p, w, wmax, b, st)
+                    : bp_go<T, Z3, 4, false>(p, w, wmax, b, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, int acc,
+hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
                               const uint32_t* wmax, void* b, hipStream_t st) {
-  const bool dbl = p->precision == DEAM_PREC_FP64;
-  if (dbl) {
-    if (acc == ACC_PACKED) return hipErrorInvalidValue;
-    return p->gd.is3d ? bp_by_channels<double, true>(p, w, n_ch, acc, wmax, b, st)
-                      : bp_by_channels<double, false>(p, w, n_ch, acc, wmax, b, st);
-  }
-  return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, acc, wmax, b, st)
-                    : bp_by_channels<float, false>(p, w, n_ch, acc, wmax, b, st);
+  if (p->precision == DEAM_PREC_FP64)
+    return p->gd.is3d ? bp_by_channels<double, true>(p, w, n_ch, nonneg, wmax, b, st)
+                      : bp_by_channels<double, false>(p, w, n_ch, nonneg, wmax, b, st);
+  return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, nonneg, wmax, b, st)
+                    : bp_by_channels<float, false>(p, w, n_ch, nonneg, wmax, b, st);
 }
 
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
