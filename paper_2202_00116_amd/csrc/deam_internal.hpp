@@ -58,8 +58,8 @@ struct Tiling {
 enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
 
 constexpr int kFpBlock = 256;
-constexpr int kBpBlock = 256;
-constexpr int kViewBatch = 16;
+constexpr int kBpBlock = 512;
+constexpr int kViewBatch = 32;
 
 // Workspace pieces (byte offsets, 256-aligned).
 struct WsLayout {

@@ -73,11 +73,11 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   const RayXY<T> t = rays[(int64_t)v * G.n_cols + k];
   const bool yd = t.yd != (T)0;
   const T Lr = (T)G.row[2 * r + 1];
-  T mw = 0, w0 = (T)0.5, imw = 0;
+  T mw = 0, w0 = (T)0.5, rmw = 0;
   if (G.is3d) {
     mw = (T)G.row[2 * r] * t.ida;
     w0 = (T)G.view[4 * v + 3] - t.sa * mw;
-    imw = mw != (T)0 ? (T)1 / fabs(mw) : (T)0;
+    rmw = mw != (T)0 ? (T)1 / mw : (T)0;
   }
   const T alo_box = (T)(yd ? loy : lox), ahi_box = (T)(yd ? hiy : hix);
   const T blo = (T)(yd ? lox : loy), bhi = (T)(yd ? hix : hiy);
@@ -91,7 +91,7 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   }
   if (G.is3d) {
     if (mw != (T)0) {
-      const T t0 = ((T)loz - w0) / mw, t1 = ((T)hiz - w0) / mw;
+      const T t0 = ((T)loz - w0) * rmw, t1 = ((T)hiz - w0) * rmw;
       alo = fmax(alo, fmin(t0, t1));
       ahi = fmin(ahi, fmax(t0, t1));
     } else if (!(w0 >= (T)loz && w0 < (T)hiz)) {
@@ -103,7 +103,7 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   ry.mb = t.mb;
   ry.w0 = w0;
   ry.mw = mw;
-  ry.imw = imw;
+  ry.imw = fabs(rmw);
   ry.La = Lr * fabs(t.ida);
   ry.Lb = Lr * t.iadb;
   ry.alo = alo;
@@ -571,6 +571,10 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       scale[c] = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
   }
 
+  T scl[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) scl[c] = (T)fmin(scale[c], 1e30);
+
   // tile rectangle (mm) and axial range
   const double X0 = G.x0 + tx0 * G.dx, X1 = G.x0 + tx1 * G.dx;
   const double Y0 = G.y0 + ty0 * G.dy, Y1 = G.y0 + ty1 * G.dy;
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
         }
       }
       s_kl[j] = kl;
-      s_nk[j] = nr > 0 ? nk : 0;
+      s_nk[j] = nk;
       s_rl[j] = rl;
       s_nr[j] = nr;
     }
@@ -630,27 +634,33 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       int run = 0;
       for (int j = 0; j < kViewBatch; ++j) {
         s_off[j] = run;
-        run += s_nk[j];
+        run += s_nk[j] * s_nr[j];
       }
       s_off[kViewBatch] = run;
     }
     __syncthreads();
     const int total = s_off[kViewBatch];
-    // one item per (view, channel); the thread walks all of its detector rows
+    // one item per (view, detector row, channel), channel fastest, so that
+    // neighbouring lanes take neighbouring rays
     for (int it = threadIdx.x; it < total; it += kBpBlock) {
+      // view of the item: the last j with s_off[j] <= it (binary search)
       int j = 0;
 #pragma unroll
-      for (int q = 1; q < kViewBatch; ++q) j += (it >= s_off[q]) ? 1 : 0;
-      const int k = s_kl[j] + (it - s_off[j]);
+      for (int step = kViewBatch / 2; step > 0; step >>= 1)
+        if (s_off[j + step] <= it) j += step;
+      const int loc = it - s_off[j];
+      const int nk = s_nk[j];
+      const int rr = loc / nk;
+      const int k = s_kl[j] + (loc - rr * nk);
+      const int r = s_rl[j] + rr;
       const int v = vb0 + j;
-      const int r0 = s_rl[j], r1 = r0 + s_nr[j];
-      for (int r = r0; r < r1; ++r) {
+      {
         Ray<T> ry;
         if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
         const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
         T ws[NCH];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) ws[c] = (T)((double)w[c * G.R + ray] * scale[c]);
+        for (int c = 0; c < NCH; ++c) ws[c] = w[c * G.R + ray] * scl[c];
         const int la = ry.ydrive ? ty0 : tx0, ha = ry.ydrive ? ty1 : tx1;
         const int lbb = ry.ydrive ? tx0 : ty0, hb = ry.ydrive ? tx1 : ty1;
         const int sa = ry.ydrive ? rs : 1, sbs = ry.ydrive ? 1 : rs;
@@ -684,7 +694,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const double val = (double)(long long)acc[c * nvox + i];
-      b[c * G.V + gi] = scale[c] > 0.0 ? (T)(val / scale[c]) : (T)0;
+      b[c * G.V + gi] = scl[c] > (T)0 ? (T)(val / (double)scl[c]) : (T)0;
     }
   }
 }
