@@ -54,27 +54,6 @@ int check_plan(const deam_plan* p) {
 // Tile of the backprojector for `bpv` bytes of accumulators per voxel:
 // tz = min(nz, 64) slices and as many columns as fit in 80 KiB of LDS with
 // rows padded to tx + 1 words (capped at 16 x 16).
-deam::Tiling choose_tiling(const deam_geometry& g, int bpv) {
-  deam::Tiling t{};
-  const int nz = g.kind == DEAM_HELICAL3D ? g.nz : 1;
-  t.tz = std::min(nz, 64);
-  const int budget = 81920 / (t.tz * bpv);   // padded columns that fit in 80 KiB (two tiles per CU)
-  int tx = 1, ty = 1;
-  while ((tx < 16 || ty < 16)) {
-    const int ntx = (tx <= ty && tx < 16) ? tx * 2 : tx;
-    const int nty = (ntx == tx) ? ty * 2 : ty;
-    if ((ntx + 1) * nty > budget) break;
-    tx = ntx;
-    ty = nty;
-  }
-  t.tx = tx;
-  t.ty = ty;
-  t.ntx = (g.nx + tx - 1) / tx;
-  t.nty = (g.ny + ty - 1) / ty;
-  t.ntz = (nz + t.tz - 1) / t.tz;
-  return t;
-}
-
 // Upper bound of max_x sum_y h(x,y): per view at most nk channels and nr rows
 // pass through one voxel, each with a chord no longer than the voxel diagonal.
 double h1_bound(const deam_geometry& g) {
@@ -243,11 +222,11 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     return fail(DEAM_ERR_HIP, "hipGetDevice failed");
   }
 
-  // geometry tables (FP64): per view [cos b, sin b, z_s, w_s], per row [zeta_r/dz, L_r]
+  // geometry tables (FP64): per view [cos b, sin b, z_s, w_s], per row [zeta_r/dz, L_r, dz/zeta_r, 0]
   const double x0 = -0.5 * g.nx * g.dx, y0 = -0.5 * g.ny * g.dy;
   const int nzv = is3d ? g.nz : 1;
   const double z0 = -0.5 * nzv * g.dz;
-  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_rows * 2);
+  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_rows * 4);
   double* tv = tab.data();
   double* tr = tv + (size_t)g.n_views * 4;
   for (int v = 0; v < g.n_views; ++v) {
@@ -261,8 +240,10 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   const double dzeta = is3d ? g.drow_iso * g.sdd / g.sid : 1.0;
   for (int r = 0; r < g.n_rows; ++r) {
     const double zeta = is3d ? ((double)r - 0.5 * (g.n_rows - 1)) * dzeta : 0.0;
-    tr[2 * r] = zeta / g.dz;
-    tr[2 * r + 1] = std::sqrt(g.sdd * g.sdd + zeta * zeta);
+    tr[4 * r] = zeta / g.dz;
+    tr[4 * r + 1] = std::sqrt(g.sdd * g.sdd + zeta * zeta);
+    tr[4 * r + 2] = zeta != 0.0 ? g.dz / zeta : 0.0;
+    tr[4 * r + 3] = 0.0;
   }
   // in-plane ray of every (view, channel), walked along its driving axis
   const size_t nvk = (size_t)g.n_views * g.n_cols;
@@ -363,7 +344,6 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
 
   p->h1_bound = h1_bound(g);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
-  for (int n = 1; n <= 4; ++n) p->tile[n] = choose_tiling(g, 8 * n);
   p->fp_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
   *out = p;
   return ok();

@@ -34,7 +34,7 @@ struct GeomDev {
   double sid, sdd, dgamma, kc;  // kc = (n_cols-1)/2 + col_offset
   double dzeta, rc;             // row pitch at the detector (mm), (n_rows-1)/2
   const double* view;           // [n_views][4]: cos b, sin b, z_s (mm), w_s (grid units)
-  const double* row;            // [n_rows][2]: zeta_r / dz (grid units), 3D ray length L_r (mm)
+  const double* row;            // [n_rows][4]: zeta_r/dz (grid units), 3D ray length L_r (mm), dz/zeta_r (0 if zeta_r = 0), 0
   const void* rays;             // RayXY<T> [n_views][n_cols] in the plan precision
   const RayXY<double>* rays64;  // FP64 copy (metal trace, FP64 plans)
   int64_t R, V;
@@ -53,6 +53,19 @@ struct EBin {
 struct Tiling {
   int tx, ty, tz;
   int ntx, nty, ntz;
+};
+
+// Tile shape of the backprojector for NCH 64-bit accumulators per voxel:
+// 16 x 16 pixels in 2D; in 3D flat 32 x 32 x (8 / NCH) slabs (rays are close
+// to the slice planes, so a wide, thin slab gives long in-tile paths).  At
+// most 80 KiB of LDS, so two tiles share a CU.
+template <bool Z3, int NCH>
+struct BpTile {
+  static constexpr int tx = Z3 ? 32 : 16;
+  static constexpr int ty = Z3 ? 32 : 16;
+  static constexpr int tz = Z3 ? 8 / NCH : 1;
+  static constexpr size_t lds_bytes = (size_t)(tx + 1) * ty * tz * NCH * 8;
+  static_assert(lds_bytes <= 81920, "backprojection tile exceeds 80 KiB");
 };
 
 enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
@@ -86,7 +99,6 @@ struct deam_plan {
   void* d_energy;                // EBin<float> or EBin<double> [nE]
   double h1_bound;               // upper bound of max_x sum_y h(x,y)
   double hmax;                   // upper bound of one h(x,y): the voxel diagonal
-  deam::Tiling tile[5];          // BP tiling for n_ch int64 words per voxel (index n_ch)
   int64_t fp_blocks;             // blocks of the ray kernels
 };
 

@@ -37,11 +37,29 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
-// max(lo, min(v, hi)) lowers to a single v_med3_i32
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return max(lo, min(v, hi)); }
-// floor and convert in one instruction
-__device__ __forceinline__ int ifloor(float x) { return __float2int_rd(x); }
+// clamp to [lo, hi] in one v_med3_i32 (the compiler emits min + max)
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(lo), "v"(hi));
+  return r;
+}
+// floor and convert in one v_cvt_flr_i32_f32 (the compiler emits floor + cvt)
+__device__ __forceinline__ int ifloor(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 __device__ __forceinline__ int ifloor(double x) { return __double2int_rd(x); }
+// clamp to [0, hi] (v_med3_f32 for float)
+__device__ __forceinline__ float clamp0(float x, float hi) { return __builtin_amdgcn_fmed3f(x, 0.f, hi); }
+__device__ __forceinline__ double clamp0(double x, double hi) { return fmin(fmax(x, 0.0), hi); }
+// min(x, hi) for finite operands, as the median of (x, hi, -3e38)
+// (v_med3_f32 for float: no canonicalisation of the loop-invariant bound
+// inside the loop)
+__device__ __forceinline__ float min_fin(float x, float hi) {
+  return __builtin_amdgcn_fmed3f(x, hi, -3.0e38f);
+}
+__device__ __forceinline__ double min_fin(double x, double hi) { return fmin(x, hi); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 
@@ -58,6 +76,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 template <typename T>
 struct Ray {
   T b0, mb;       // lateral grid coordinate b(a) = b0 + a*mb
+  T imb;          // 1/mb (huge when mb = 0)
   T w0, mw, imw;  // axial grid coordinate w(a) = w0 + a*mw, imw = 1/|mw|
   T La, Lb;       // mm of ray per unit of a, per unit of b
   T alo, ahi;     // range of a inside the clip box
@@ -72,10 +91,10 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
                                          int hiy, int hiz, Ray<T>& ry) {
   const RayXY<T> t = rays[(int64_t)v * G.n_cols + k];
   const bool yd = t.yd != (T)0;
-  const T Lr = (T)G.row[2 * r + 1];
+  const T Lr = (T)G.row[4 * r + 1];
   T mw = 0, w0 = (T)0.5, rmw = 0;
   if (G.is3d) {
-    mw = (T)G.row[2 * r] * t.ida;
+    mw = (T)G.row[4 * r] * t.ida;
     w0 = (T)G.view[4 * v + 3] - t.sa * mw;
     rmw = mw != (T)0 ? (T)1 / mw : (T)0;
   }
@@ -101,6 +120,7 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   if (!(ahi > alo)) return false;
   ry.b0 = t.b0;
   ry.mb = t.mb;
+  ry.imb = t.imb;
   ry.w0 = w0;
   ry.mw = mw;
   ry.imw = fabs(rmw);
@@ -535,13 +555,32 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
   return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
 }
 
+// One backprojector for both geometries.  A workgroup owns a tile of
+// BpTile<Z3, NCH> voxels in LDS and scatters every ray that meets it, view
+// batch by view batch; work items are (view, detector row, channel) with the
+// channel fastest, so neighbouring lanes walk neighbouring rays.
+//
+// Each lane walks its ray through the tile one plane step of the driving
+// axis at a time, carrying the lateral pixel and coordinate from the end of
+// the previous step: a step costs one lateral floor, and splits into at most
+// two segments (pixel A, then pixel B after the lateral plane crossing).
+// Lengths are kept in units of the driving axis; the weights carry the mm per
+// unit.  In 3D the rare steps that cross an axial plane (or leave the tile's
+// slices) are only flagged in a bit mask during the walk and scattered
+// afterwards through the general walk_row, so that the lanes of a wave stay
+// on the common path.
 template <typename T, bool Z3, int NCH, bool NONNEG>
 __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
                                                  double hmax, T* __restrict__ b) {
+  using BT = BpTile<Z3, NCH>;
+  constexpr int RS = BT::tx + 1;       // padded row stride (words)
+  constexpr int TXY = RS * BT::ty;     // words per slice
+  constexpr int NVOX = TXY * BT::tz;   // words per channel
+  static_assert(BT::tx <= 32 && BT::ty <= 32, "deferred steps live in a 32-bit mask");
   extern __shared__ unsigned long long acc[];
   __shared__ float s_kap[kViewBatch][4];
-  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_nr[kViewBatch];
+  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch];
   __shared__ int s_off[kViewBatch + 1];
   const RayXY<T>* __restrict__ rays =
       (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
@@ -550,30 +589,26 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   // rays a tile reads are mostly read by other tiles of the same L2
   const int t = xcd_block(blockIdx.x, gridDim.x);
   const int tix = t % TL.ntx, tiy = (t / TL.ntx) % TL.nty, tiz = t / (TL.ntx * TL.nty);
-  const int tx0 = tix * TL.tx, ty0 = tiy * TL.ty, tz0 = tiz * TL.tz;
-  const int tx1 = min(tx0 + TL.tx, G.nx), ty1 = min(ty0 + TL.ty, G.ny);
-  const int tz1 = min(tz0 + TL.tz, G.is3d ? G.nz : 1);
-  // LDS layout: acc[c][z][y][x] with a row stride of tx + 1 words, so that
-  // lanes walking neighbouring rays of one view (neighbouring x for rays
-  // driven along y, neighbouring y for rays driven along x) hit distinct banks
-  const int rs = TL.tx + 1;
-  const int txy = rs * TL.ty;
-  const int nvox = txy * TL.tz;
-  for (int i = threadIdx.x; i < nvox * NCH; i += kBpBlock) acc[i] = 0ull;
-
-  double scale[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const float m = __uint_as_float(wmax[c]);
-    if (sizeof(T) == 4)
-      scale[c] = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
-    else
-      scale[c] = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
-  }
+  const int tx0 = tix * BT::tx, ty0 = tiy * BT::ty, tz0 = tiz * BT::tz;
+  const int tx1 = min(tx0 + BT::tx, G.nx), ty1 = min(ty0 + BT::ty, G.ny);
+  const int tz1 = min(tz0 + BT::tz, G.is3d ? G.nz : 1);
+  // LDS layout acc[c][z][y][x], row stride tx + 1 words: lanes walking
+  // neighbouring rays of one view (neighbouring x for rays driven along y,
+  // neighbouring y for rays driven along x) hit distinct banks; the channel
+  // stride is a compile-time constant, so it folds into the instruction offset
+  for (int i = threadIdx.x; i < NVOX * NCH; i += kBpBlock) acc[i] = 0ull;
 
   T scl[NCH];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) scl[c] = (T)fmin(scale[c], 1e30);
+  for (int c = 0; c < NCH; ++c) {
+    const float m = __uint_as_float(wmax[c]);
+    double s;
+    if (sizeof(T) == 4)
+      s = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
+    else
+      s = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
+    scl[c] = (T)fmin(s, 1e30);
+  }
 
   // tile rectangle (mm) and axial range
   const double X0 = G.x0 + tx0 * G.dx, X1 = G.x0 + tx1 * G.dx;
@@ -597,10 +632,12 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       s_kap[j][cn] = kap;
     }
     __syncthreads();
-    if (threadIdx.x < kViewBatch) {
+    // channel and row ranges of each view, and their exclusive prefix sum
+    // (one wave)
+    if (threadIdx.x < 64) {
       const int j = threadIdx.x, v = vb0 + j;
       int kl = 0, nk = 0, rl = 0, nr = 0;
-      if (v < G.n_views) {
+      if (j < kViewBatch && v < G.n_views) {
         const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
         const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
         kl = max((int)ceilf(kmn - 0.01f), 0);
@@ -624,24 +661,22 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
           nr = 1;
         }
       }
-      s_kl[j] = kl;
-      s_nk[j] = nk;
-      s_rl[j] = rl;
-      s_nr[j] = nr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int j = 0; j < kViewBatch; ++j) {
-        s_off[j] = run;
-        run += s_nk[j] * s_nr[j];
+      int run = nk * nr;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(run, d);
+        if (j >= d) run += u;
       }
-      s_off[kViewBatch] = run;
+      if (j < kViewBatch) {
+        s_kl[j] = kl;
+        s_nk[j] = nk;
+        s_rl[j] = rl;
+        s_off[j + 1] = run;
+      }
+      if (j == 0) s_off[0] = 0;
     }
     __syncthreads();
     const int total = s_off[kViewBatch];
-    // one item per (view, detector row, channel), channel fastest, so that
-    // neighbouring lanes take neighbouring rays
     for (int it = threadIdx.x; it < total; it += kBpBlock) {
       // view of the item: the last j with s_off[j] <= it (binary search)
       int j = 0;
@@ -654,46 +689,98 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       const int k = s_kl[j] + (loc - rr * nk);
       const int r = s_rl[j] + rr;
       const int v = vb0 + j;
-      {
-        Ray<T> ry;
-        if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
-        const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
-        T ws[NCH];
+      Ray<T> ry;
+      if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
+      const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
+      T wa[NCH];   // weight x scale x mm per unit of the driving axis
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) ws[c] = w[c * G.R + ray] * scl[c];
-        const int la = ry.ydrive ? ty0 : tx0, ha = ry.ydrive ? ty1 : tx1;
-        const int lbb = ry.ydrive ? tx0 : ty0, hb = ry.ydrive ? tx1 : ty1;
-        const int sa = ry.ydrive ? rs : 1, sbs = ry.ydrive ? 1 : rs;
-        // accumulators are channel-major (acc[c][voxel]) so that lanes at
-        // neighbouring voxels hit neighbouring LDS banks
-        auto visit = [&](int ia, int ib, int iw, T h) {
-          const int li = (iw - tz0) * txy + (ia - la) * sa + (ib - lbb) * sbs;
+      for (int c = 0; c < NCH; ++c) wa[c] = w[c * G.R + ray] * scl[c] * ry.La;
+      const bool yd = ry.ydrive != 0;
+      const int la = yd ? ty0 : tx0;
+      const int lbb = yd ? tx0 : ty0, hb = yd ? tx1 : ty1;
+      const int sa = yd ? RS : 1, sbs = yd ? 1 : RS;
+      // lb: byte offset of the voxel in channel 0; da: length in units of
+      // the driving axis
+      char* const accb = reinterpret_cast<char*>(acc);
+      auto deposit = [&](int lb, T da) {
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            if constexpr (NONNEG && sizeof(T) == 4)
-              atomicAdd(&acc[c * nvox + li], to_fixed_nonneg((float)h, (float)ws[c]));
-            else
-              atomicAdd(&acc[c * nvox + li], to_fixed(h * ws[c]));
+        for (int c = 0; c < NCH; ++c) {
+          unsigned long long* const a =
+              reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + c * NVOX * 8);
+          if constexpr (NONNEG && sizeof(T) == 4)
+            atomicAdd(a, to_fixed_nonneg((float)da, (float)wa[c]));
+          else
+            atomicAdd(a, to_fixed(da * wa[c]));
+        }
+      };
+      const int q0 = ifloor(ry.alo) - la;        // first plane step (tile-relative)
+      const int q1 = -ifloor(-ry.ahi) - la;      // one past the last
+      T tp = ry.alo;                             // start of the current step
+      T bp = fma(tp, ry.mb, ry.b0);              // lateral coordinate there
+      T fa = (T)(la + q0);
+      int A = clampi(ifloor(bp), lbb, hb - 1);
+      const int sb8 = 8 * sbs;
+      // byte offset of lateral index 0 in the current plane row and slice
+      int row8 = 8 * (q0 * sa - lbb * sbs);
+      int C = 0;
+      if constexpr (Z3) {
+        C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), tz0, tz1 - 1);
+        row8 += 8 * (C - tz0) * TXY;
+      }
+      uint32_t rest = 0;   // 3D: steps left to the general walk
+      for (int q = q0; q < q1; ++q) {
+        fa += (T)1;
+        const T tn = min_fin(fa, ry.ahi);
+        const T bn = fma(tn, ry.mb, ry.b0);
+        const int B = clampi(ifloor(bn), lbb, hb - 1);
+        bool flat = true;
+        if constexpr (Z3) {
+          const int D = ifloor(fma(tn, ry.mw, ry.w0));
+          if (D != C) {
+            flat = false;
+            rest |= 1u << q;
+            const int C1 = clampi(D, tz0, tz1 - 1);
+            row8 += 8 * (C1 - C) * TXY;
+            C = C1;
           }
+        }
+        if (flat) {
+          const T ds = tn - tp;
+          // the part of the step before the lateral crossing (all of it when
+          // the step stays in one pixel)
+          const T dA = (B == A) ? ds : clamp0(((T)max(A, B) - bp) * ry.imb, ds);
+          deposit(__mul24(A, sb8) + row8, dA);
+          if (B != A) deposit(__mul24(B, sb8) + row8, ds - dA);
+        }
+        row8 += 8 * sa;
+        A = B;
+        tp = tn;
+        bp = bn;
+      }
+      if constexpr (Z3) {
+        const T iLa = (T)1 / ry.La;
+        auto visit3 = [&](int ia, int ib, int iw, T h) {
+          deposit(8 * ((iw - tz0) * TXY + (ia - la) * sa + (ib - lbb) * sbs), h * iLa);
         };
-        // every lane steps through all plane steps of the tile (steps outside
-        // its ray are empty), so at each step the lanes of a wave touch
-        // neighbouring accumulators
-        for (int ia = la; ia < ha; ++ia) walk_row<T, Z3, true>(ry, ia, lbb, hb, tz0, tz1, visit);
+        while (rest != 0u) {
+          const int q = __ffs(rest) - 1;
+          rest &= rest - 1u;
+          walk_row<T, true, true>(ry, la + q, lbb, hb, tz0, tz1, visit3);
+        }
       }
     }
     __syncthreads();
   }
 
   // write the tile
-  for (int i = threadIdx.x; i < nvox; i += kBpBlock) {
-    const int lx = i % rs, ly = (i / rs) % TL.ty, lz = i / txy;
+  for (int i = threadIdx.x; i < NVOX; i += kBpBlock) {
+    const int lx = i % RS, ly = (i / RS) % BT::ty, lz = i / TXY;
     const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
-    if (lx >= TL.tx || gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
+    if (lx >= BT::tx || gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
     const int64_t gi = ((int64_t)gz * G.ny + gy) * G.nx + gx;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-      const double val = (double)(long long)acc[c * nvox + i];
+      const double val = (double)(long long)acc[c * NVOX + i];
       b[c * G.V + gi] = scl[c] > (T)0 ? (T)(val / (double)scl[c]) : (T)0;
     }
   }
@@ -906,8 +993,12 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
 template <typename T, bool Z3, int NCH, bool NONNEG>
 static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
                         hipStream_t st) {
-  const Tiling& TL = p->tile[NCH];
-  const size_t lds = (size_t)(TL.tx + 1) * TL.ty * TL.tz * NCH * 8;
+  using BT = BpTile<Z3, NCH>;
+  Tiling TL{BT::tx, BT::ty, BT::tz, 0, 0, 0};
+  TL.ntx = (p->gd.nx + BT::tx - 1) / BT::tx;
+  TL.nty = (p->gd.ny + BT::ty - 1) / BT::ty;
+  TL.ntz = ((Z3 ? p->gd.nz : 1) + BT::tz - 1) / BT::tz;
+  const size_t lds = BT::lds_bytes;
   const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
   auto kern = k_bp<T, Z3, NCH, NONNEG>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
