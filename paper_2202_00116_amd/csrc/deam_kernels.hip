@@ -573,10 +573,18 @@ template <typename T, bool Z3, int NCH, bool NONNEG>
 __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
                                                  double hmax, T* __restrict__ b) {
-  using BT = BpTile<Z3, NCH>;
+  // Packed accumulation (float plans, the 4 non-negative AM channels): the
+  // LDS word of a voxel holds two channels as 32-bit halves, so one atomic
+  // adds two terms.  The scale is chosen so that the sum over one view batch
+  // stays below 2^32 in each half (no carry into the upper half); after every
+  // batch each thread moves the words it owns into 64-bit register totals.
+  constexpr bool PK = NONNEG && sizeof(T) == 4 && NCH == 4;
+  using BT = BpTile<Z3, NCH, PK>;
   constexpr int RS = BT::tx + 1;       // padded row stride (words)
   constexpr int TXY = RS * BT::ty;     // words per slice
-  constexpr int NVOX = TXY * BT::tz;   // words per channel
+  constexpr int NVOX = TXY * BT::tz;   // words per channel (pair of channels when PK)
+  constexpr int NW = NVOX * BT::wpv;   // LDS words
+  constexpr int NOWN = PK ? (NW + kBpBlock - 1) / kBpBlock : 1;
   static_assert(BT::tx <= 32 && BT::ty <= 32, "deferred steps live in a 32-bit mask");
   extern __shared__ unsigned long long acc[];
   __shared__ float s_kap[kViewBatch][4];
@@ -596,14 +604,22 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   // neighbouring rays of one view (neighbouring x for rays driven along y,
   // neighbouring y for rays driven along x) hit distinct banks; the channel
   // stride is a compile-time constant, so it folds into the instruction offset
-  for (int i = threadIdx.x; i < NVOX * NCH; i += kBpBlock) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < NW; i += kBpBlock) acc[i] = 0ull;
+  unsigned long long tot[2 * NOWN];   // PK: 64-bit totals of the owned words
+#pragma unroll
+  for (int o = 0; o < 2 * NOWN; ++o) tot[o] = 0ull;
 
+  // h1 bounds max_x sum_y h(x,y) over all views; a batch of kViewBatch views
+  // contributes at most the fraction kViewBatch / n_views of it
+  const double hb = h1 * (double)min(kViewBatch, G.n_views) / (double)G.n_views;
   T scl[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const float m = __uint_as_float(wmax[c]);
     double s;
-    if (sizeof(T) == 4)
+    if (PK)   // 2^32 - 2^20: room for the rounding of every term
+      s = (m > 0.f && hb > 0.0) ? 4293918720.0 / (hb * (double)m) : 0.0;
+    else if (sizeof(T) == 4)
       s = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
     else
       s = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
@@ -703,14 +719,25 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       // the driving axis
       char* const accb = reinterpret_cast<char*>(acc);
       auto deposit = [&](int lb, T da) {
+        if constexpr (PK) {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          unsigned long long* const a =
-              reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + c * NVOX * 8);
-          if constexpr (NONNEG && sizeof(T) == 4)
-            atomicAdd(a, to_fixed_nonneg((float)da, (float)wa[c]));
-          else
-            atomicAdd(a, to_fixed(da * wa[c]));
+          for (int p = 0; p < 2; ++p) {
+            unsigned long long* const a =
+                reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + p * NVOX * 8);
+            const uint32_t lo = (uint32_t)fmaf((float)da, (float)wa[2 * p], 0.5f);
+            const uint32_t hi = (uint32_t)fmaf((float)da, (float)wa[2 * p + 1], 0.5f);
+            atomicAdd(a, ((unsigned long long)hi << 32) | lo);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            unsigned long long* const a =
+                reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + c * NVOX * 8);
+            if constexpr (NONNEG && sizeof(T) == 4)
+              atomicAdd(a, to_fixed_nonneg((float)da, (float)wa[c]));
+            else
+              atomicAdd(a, to_fixed(da * wa[c]));
+          }
         }
       };
       const int q0 = ifloor(ry.alo) - la;        // first plane step (tile-relative)
@@ -770,6 +797,38 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       }
     }
     __syncthreads();
+    if constexpr (PK) {
+      // move the batch into the 64-bit totals; the next batch deposits only
+      // after the barrier that follows its view set-up
+#pragma unroll
+      for (int o = 0; o < NOWN; ++o) {
+        const int i = threadIdx.x + o * kBpBlock;
+        if (i < NW) {
+          const unsigned long long x = acc[i];
+          acc[i] = 0ull;
+          tot[2 * o] += (uint32_t)x;
+          tot[2 * o + 1] += x >> 32;
+        }
+      }
+    }
+  }
+
+  if constexpr (PK) {
+#pragma unroll
+    for (int o = 0; o < NOWN; ++o) {
+      const int i = threadIdx.x + o * kBpBlock;
+      if (i >= NW) continue;
+      const int p = i >= NVOX ? 1 : 0;
+      const int vi = i - p * NVOX;
+      const int lx = vi % RS, ly = (vi / RS) % BT::ty, lz = vi / TXY;
+      const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
+      if (lx >= BT::tx || gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
+      const int64_t gi = ((int64_t)gz * G.ny + gy) * G.nx + gx;
+      const T slo = p ? scl[2] : scl[0], shi = p ? scl[3] : scl[1];
+      b[(2 * p) * G.V + gi] = slo > (T)0 ? (T)((double)tot[2 * o] / (double)slo) : (T)0;
+      b[(2 * p + 1) * G.V + gi] = shi > (T)0 ? (T)((double)tot[2 * o + 1] / (double)shi) : (T)0;
+    }
+    return;
   }
 
   // write the tile
@@ -993,7 +1052,7 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
 template <typename T, bool Z3, int NCH, bool NONNEG>
 static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
                         hipStream_t st) {
-  using BT = BpTile<Z3, NCH>;
+  using BT = BpTile<Z3, NCH, NONNEG && sizeof(T) == 4 && NCH == 4>;
   Tiling TL{BT::tx, BT::ty, BT::tz, 0, 0, 0};
   TL.ntx = (p->gd.nx + BT::tx - 1) / BT::tx;
   TL.nty = (p->gd.ny + BT::ty - 1) / BT::ty;
