@@ -63,6 +63,15 @@ __device__ __forceinline__ double min_fin(double x, double hi) { return fmin(x, 
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 
+// Minimum / maximum over the lanes of the wave, as a wave-uniform value.
+// Must be reached by all 64 lanes (the reduction reads lanes 0 and 32).
+__device__ __forceinline__ int wave_min(int x) {
+  return __builtin_amdgcn_readfirstlane(__ockl_wfred_min_i32(x));
+}
+__device__ __forceinline__ int wave_max(int x) {
+  return __builtin_amdgcn_readfirstlane(__ockl_wfred_max_i32(x));
+}
+
 // Logical block index that gives each XCD a contiguous range of blocks
 // (blocks are dispatched round-robin over the 8 XCDs).
 __device__ __forceinline__ int xcd_block(int b, int nb) {
@@ -197,108 +206,153 @@ __device__ __forceinline__ void neumaier(T& s, T& c, T x) {
 // cp holds the packed image twice: natural order at element 0 and x-major at
 // element xoff; rays driven along y read the first copy, rays driven along
 // x the second, so neighbouring lanes gather neighbouring addresses.
-// Plane steps fully inside the ray's range (va = ia, vb = ia + 1) in the same
-// slice are processed four at a time with all gathers issued before the
-// accumulation; partial end steps and steps with an axial crossing go
-// through walk_row (the arithmetic of both paths is identical).
+// The walk carries the lateral pixel and coordinate from one plane step to
+// the next (one lateral floor per step) and keeps lengths in units of the
+// driving axis; the sums are scaled by the mm per unit at the end.  Steps go
+// four at a time with all gathers issued before the accumulation.  In 3D a
+// step that crosses an axial plane is left out of the fast walk and recorded
+// in a 64-bit mask; every 16 groups (a point common to all lanes still
+// walking) and at the end, the recorded steps are summed through the general
+// walk_row.
+// Called by all lanes of the wave (valid = false: no ray, result 0).
 template <typename T, bool Z3>
 __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
                             const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff, int v,
-                            int r, int k, T& l1, T& l2) {
+                            int r, int k, bool valid, T& l1, T& l2) {
   using T2 = typename Vec2<T>::type;
+  constexpr uint32_t E = sizeof(T2);
   l1 = 0;
   l2 = 0;
-  Ray<T> ry;
+  Ray<T> ry{};
   const int nzz = G.is3d ? G.nz : 1;
-  if (!make_ray<T>(G, rays, v, r, k, 0, 0, 0, G.nx, G.ny, nzz, ry)) return;
+  const bool hit = valid && make_ray<T>(G, rays, v, r, k, 0, 0, 0, G.nx, G.ny, nzz, ry);
   const uint32_t base = ry.ydrive ? 0u : xoff;
   const int nb = ry.ydrive ? G.nx : G.ny;
-  const int na = ry.ydrive ? G.ny : G.nx;
   const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
+  const uint32_t rstep = (uint32_t)nb * E;
+  const char* __restrict__ cpb = (const char*)cp;
   T s1 = 0, c1 = 0, s2 = 0, c2 = 0, p1 = 0, p2 = 0;
-  auto visit = [&](int ia, int ib, int iw, T h) {
-    const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
-    p1 = fma(h, cv.x, p1);
-    p2 = fma(h, cv.y, p2);
-  };
   auto flush = [&]() {
     neumaier(s1, c1, p1);
     neumaier(s2, c2, p2);
     p1 = 0;
     p2 = 0;
   };
-  const int ia0 = max(ifloor(ry.alo), 0);
-  const int ia1 = min((int)ceil(ry.ahi) - 1, na - 1);
-  const int fa = max((int)ceil(ry.alo), ia0);            // first full step
-  const int fb = min(ifloor(ry.ahi) - 1, ia1);       // last full step
-  int ia = ia0;
-  for (; ia < fa && ia <= ia1; ++ia) walk_row<T, Z3, false>(ry, ia, 0, nb, 0, nzz, visit);
-  const T La = ry.La;
-  int groups = 0;
-  for (; ia + 3 <= fb; ia += 4) {
-    T bq[5];
-    int F[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      bq[q] = fma((T)(ia + q), ry.mb, ry.b0);
-      F[q] = clampi(ifloor(bq[q]), 0, nb - 1);
+  // plane steps [q0, q1); empty for a lane without a ray
+  const int q0 = hit ? ifloor(ry.alo) : (1 << 30);
+  const int q1 = hit ? -ifloor(-ry.ahi) : -(1 << 30);
+  T tp = ry.alo;                                         // start of the current step
+  T bp = fma(tp, ry.mb, ry.b0);                          // lateral coordinate there
+  T fa = (T)q0;
+  int A = clampi(ifloor(bp), 0, nb - 1);
+  int C = 0;
+  // byte offset of lateral index 0 in the current plane row and slice
+  uint32_t row = (base + (uint32_t)q0 * (uint32_t)nb) * E;
+  if constexpr (Z3) {
+    C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), 0, nzz - 1);
+    row += (uint32_t)C * plane * E;
+  }
+  uint64_t rest = 0;   // 3D: deferred steps, bit = step - qw
+  int qw = q0;
+  // one plane step: gather offsets and lengths (zero when deferred or when
+  // the step lies outside the ray's range, with a valid address)
+  auto step = [&](int q, uint32_t& oA, uint32_t& oB, T& dA, T& dB) {
+    if (q < q0 || q >= q1) {
+      oA = 0u;
+      oB = 0u;
+      dA = (T)0;
+      dB = (T)0;
+      return;
     }
-    int iw = 0;
+    fa += (T)1;
+    const T tn = min_fin(fa, ry.ahi);
+    const T bn = fma(tn, ry.mb, ry.b0);
+    const int B = clampi(ifloor(bn), 0, nb - 1);
+    T ds = tn - tp;
+    const uint32_t rq = row;
+    row += rstep;
     if constexpr (Z3) {
-      const int G0 = clampi(ifloor(fma((T)ia, ry.mw, ry.w0)), 0, nzz - 1);
-      const int G4 = clampi(ifloor(fma((T)(ia + 4), ry.mw, ry.w0)), 0, nzz - 1);
-      if (G0 != G4) {
-#pragma unroll 1
-        for (int q = 0; q < 4; ++q) walk_row<T, Z3, false>(ry, ia + q, 0, nb, 0, nzz, visit);
-        if (++groups == 4) {
-          flush();
-          groups = 0;
-        }
-        continue;
+      const int D = ifloor(fma(tn, ry.mw, ry.w0));
+      if (D != C) {
+        rest |= 1ull << (q - qw);
+        ds = (T)0;
+        const int D1 = clampi(D, 0, nzz - 1);
+        row += (uint32_t)((D1 - C) * (int)plane) * E;
+        C = D1;
       }
-      iw = G0;
     }
-    // 32-bit byte offsets from the uniform base (the packed images are far
-    // below 4 GiB; the plan checks it)
+    const T a = (B == A) ? ds : clamp0(((T)max(A, B) - bp) * ry.imb, ds);
+    dA = a;
+    dB = ds - a;
+    oA = rq + (uint32_t)A * E;
+    oB = rq + (uint32_t)B * E;
+    A = B;
+    bp = bn;
+    tp = tn;
+  };
+  const T iLa = (T)1 / ry.La;
+  auto visit = [&](int ia, int ib, int iw, T h) {
+    const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
+    p1 = fma(h * iLa, cv.x, p1);
+    p2 = fma(h * iLa, cv.y, p2);
+  };
+  auto fixup = [&]() {
+    while (rest != 0ull) {
+      const int bit = __ffsll((unsigned long long)rest) - 1;
+      rest &= rest - 1ull;
+      walk_row<T, true, false>(ry, qw + bit, 0, nb, 0, nzz, visit);
+    }
+  };
+  // the lanes of a wave walk the same plane rows together (a common range,
+  // lanes idle outside their own), so that their gathers share cache lines
+  const int qlo = wave_min(q0), qhi = wave_max(q1);
+  if (qlo >= qhi) return;
+  qw = qlo;
+  int q = qlo;
+  int groups = 0;
+  for (; q + 4 <= qhi; q += 4) {
     uint32_t oA[4], oB[4];
-    T hA[4], hB[4];
-    const uint32_t row0 =
-        (base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb) * (uint32_t)sizeof(T2);
-    const uint32_t rstep = (uint32_t)nb * (uint32_t)sizeof(T2);
+    T dA[4], dB[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int A = F[q];
-      const int B = clampi(F[q + 1], A - 1, A + 1);
-      const T split = fmin(fabs((T)max(A, B) - bq[q]) * ry.Lb, La);
-      hA[q] = (A == B) ? La : split;
-      hB[q] = La - hA[q];
-      const uint32_t rq = row0 + (uint32_t)q * rstep;
-      oA[q] = rq + (uint32_t)A * (uint32_t)sizeof(T2);
-      oB[q] = rq + (uint32_t)B * (uint32_t)sizeof(T2);
-    }
+    for (int s = 0; s < 4; ++s) step(q + s, oA[s], oB[s], dA[s], dB[s]);
     T2 vA[4], vB[4];
-    const char* __restrict__ cpb = (const char*)cp;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      vA[q] = *(const T2*)(cpb + oA[q]);
-      vB[q] = *(const T2*)(cpb + oB[q]);
+    for (int s = 0; s < 4; ++s) {
+      vA[s] = *(const T2*)(cpb + oA[s]);
+      vB[s] = *(const T2*)(cpb + oB[s]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      p1 = fma(hA[q], vA[q].x, p1);
-      p2 = fma(hA[q], vA[q].y, p2);
-      p1 = fma(hB[q], vB[q].x, p1);
-      p2 = fma(hB[q], vB[q].y, p2);
+    for (int s = 0; s < 4; ++s) {
+      p1 = fma(dA[s], vA[s].x, p1);
+      p2 = fma(dA[s], vA[s].y, p2);
+      p1 = fma(dB[s], vB[s].x, p1);
+      p2 = fma(dB[s], vB[s].y, p2);
     }
-    if (++groups == 4) {
-      flush();
-      groups = 0;
+    ++groups;
+    if ((groups & 3) == 0) flush();
+    if constexpr (Z3) {
+      if ((groups & 15) == 0) {
+        fixup();
+        qw = q + 4;
+      }
     }
   }
-  for (; ia <= ia1; ++ia) walk_row<T, Z3, false>(ry, ia, 0, nb, 0, nzz, visit);
+  for (; q < qhi; ++q) {
+    uint32_t oA, oB;
+    T dA, dB;
+    step(q, oA, oB, dA, dB);
+    const T2 vA = *(const T2*)(cpb + oA), vB = *(const T2*)(cpb + oB);
+    p1 = fma(dA, vA.x, p1);
+    p2 = fma(dA, vA.y, p2);
+    p1 = fma(dB, vB.x, p1);
+    p2 = fma(dB, vB.y, p2);
+  }
+  if constexpr (Z3) fixup();
   flush();
-  l1 = s1 + c1;
-  l2 = s2 + c2;
+  if (hit) {
+    l1 = (s1 + c1) * ry.La;
+    l2 = (s2 + c2) * ry.La;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -451,14 +505,17 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
   const bool active = ray < G.R;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
-  if (active) {
-    const int k = (int)(ray % G.n_cols);
-    const int rv = (int)(ray / G.n_cols);
+  {
+    const int64_t ra = active ? ray : 0;
+    const int k = (int)(ra % G.n_cols);
+    const int rv = (int)(ra / G.n_cols);
     const int r = rv % G.n_rows, v = rv / G.n_rows;
     T l1, l2;
     const RayXY<T>* rays = (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
-    project_ray<T, Z3>(G, rays, cp, xoff, v, r, k, l1, l2);
-    if constexpr (MODE == PM_L) {
+    // all lanes of the wave take part in the walk (lanes past the last ray idle)
+    project_ray<T, Z3>(G, rays, cp, xoff, v, r, k, active, l1, l2);
+    if (!active) {
+    } else if constexpr (MODE == PM_L) {
       out[ray] = l1;
       if (nout > 1) out[G.R + ray] = l2;
     } else if constexpr (MODE == PM_TRACE) {
