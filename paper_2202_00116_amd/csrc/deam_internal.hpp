@@ -60,8 +60,14 @@ struct Tiling {
 // wide, thin slab gives long in-tile paths).  PK: two channels share one
 // 64-bit LDS word (non-negative weights, see the kernel).  At most 80 KiB of
 // LDS, so two tiles share a CU.
+// Threads per tile: 256 in 2D, so that all tiles of a 512 x 512 image are
+// resident at once (four per CU); 512 in 3D.
+template <bool Z3>
+constexpr int bp_block() { return Z3 ? 512 : 256; }
+
 template <bool Z3, int NCH, bool PK>
 struct BpTile {
+  static constexpr int block = bp_block<Z3>();
   static constexpr int wpv = PK ? NCH / 2 : NCH;   // 64-bit LDS words per voxel
   static constexpr int tx = Z3 ? 32 : 16;
   static constexpr int ty = Z3 ? 32 : 16;
@@ -73,7 +79,6 @@ struct BpTile {
 enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
 
 constexpr int kFpBlock = 256;
-constexpr int kBpBlock = 512;
 constexpr int kViewBatch = 32;
 
 // Workspace pieces (byte offsets, 256-aligned).

@@ -627,7 +627,7 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
 // afterwards through the general walk_row, so that the lanes of a wave stay
 // on the common path.
 template <typename T, bool Z3, int NCH, bool NONNEG>
-__global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
+__global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
                                                  double hmax, T* __restrict__ b) {
   // Packed accumulation (float plans, the 4 non-negative AM channels): the
@@ -641,7 +641,8 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   constexpr int TXY = RS * BT::ty;     // words per slice
   constexpr int NVOX = TXY * BT::tz;   // words per channel (pair of channels when PK)
   constexpr int NW = NVOX * BT::wpv;   // LDS words
-  constexpr int NOWN = PK ? (NW + kBpBlock - 1) / kBpBlock : 1;
+  constexpr int NT = BT::block;         // threads per tile
+  constexpr int NOWN = PK ? (NW + NT - 1) / NT : 1;
   static_assert(BT::tx <= 32 && BT::ty <= 32, "deferred steps live in a 32-bit mask");
   extern __shared__ unsigned long long acc[];
   __shared__ float s_kap[kViewBatch][4];
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   // neighbouring rays of one view (neighbouring x for rays driven along y,
   // neighbouring y for rays driven along x) hit distinct banks; the channel
   // stride is a compile-time constant, so it folds into the instruction offset
-  for (int i = threadIdx.x; i < NW; i += kBpBlock) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < NW; i += NT) acc[i] = 0ull;
   unsigned long long tot[2 * NOWN];   // PK: 64-bit totals of the owned words
 #pragma unroll
   for (int o = 0; o < 2 * NOWN; ++o) tot[o] = 0ull;
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
     }
     __syncthreads();
     const int total = s_off[kViewBatch];
-    for (int it = threadIdx.x; it < total; it += kBpBlock) {
+    for (int it = threadIdx.x; it < total; it += NT) {
       // view of the item: the last j with s_off[j] <= it (binary search)
       int j = 0;
 #pragma unroll
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
       // after the barrier that follows its view set-up
 #pragma unroll
       for (int o = 0; o < NOWN; ++o) {
-        const int i = threadIdx.x + o * kBpBlock;
+        const int i = threadIdx.x + o * NT;
         if (i < NW) {
           const unsigned long long x = acc[i];
           acc[i] = 0ull;
@@ -873,7 +874,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   if constexpr (PK) {
 #pragma unroll
     for (int o = 0; o < NOWN; ++o) {
-      const int i = threadIdx.x + o * kBpBlock;
+      const int i = threadIdx.x + o * NT;
       if (i >= NW) continue;
       const int p = i >= NVOX ? 1 : 0;
       const int vi = i - p * NVOX;
@@ -889,7 +890,7 @@ __global__ __launch_bounds__(kBpBlock) void k_bp(GeomDev G, Tiling TL, const T* 
   }
 
   // write the tile
-  for (int i = threadIdx.x; i < NVOX; i += kBpBlock) {
+  for (int i = threadIdx.x; i < NVOX; i += NT) {
     const int lx = i % RS, ly = (i / RS) % BT::ty, lz = i / TXY;
     const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
     if (lx >= BT::tx || gx >= tx1 || gy >= ty1 || gz >= tz1) continue;
@@ -1120,7 +1121,7 @@ static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax,
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nt), dim3(kBpBlock), lds, st, p->gd, TL, (const T*)w, wmax,
+  hipLaunchKernelGGL(kern, dim3(nt), dim3(BT::block), lds, st, p->gd, TL, (const T*)w, wmax,
                      p->h1_bound, p->hmax, (T*)b);
   return hipGetLastError();
 }
