@@ -63,6 +63,9 @@ __device__ __forceinline__ double min_fin(double x, double hi) { return fmin(x, 
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 
+template <bool PK> struct QType { using type = unsigned long long; };
+template <> struct QType<true> { using type = uint32_t; };
+
 // Minimum / maximum over the lanes of the wave, as a wave-uniform value.
 // Must be reached by all 64 lanes (the reduction reads lanes 0 and 32).
 __device__ __forceinline__ int wave_min(int x) {
@@ -774,30 +777,44 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
       const int lbb = yd ? tx0 : ty0, hb = yd ? tx1 : ty1;
       const int sa = yd ? RS : 1, sbs = yd ? 1 : RS;
       // lb: byte offset of the voxel in channel 0; da: length in units of
-      // the driving axis
+      // the driving axis; quantised terms are 32-bit halves when packed,
+      // 64-bit words otherwise
+      using QT = typename QType<PK>::type;
       char* const accb = reinterpret_cast<char*>(acc);
-      auto deposit = [&](int lb, T da) {
-        if constexpr (PK) {
+      auto quant = [&](T da, QT* qv) {
 #pragma unroll
-          for (int p = 0; p < 2; ++p) {
-            unsigned long long* const a =
-                reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + p * NVOX * 8);
-            const uint32_t lo = (uint32_t)fmaf((float)da, (float)wa[2 * p], 0.5f);
-            const uint32_t hi = (uint32_t)fmaf((float)da, (float)wa[2 * p + 1], 0.5f);
-            atomicAdd(a, ((unsigned long long)hi << 32) | lo);
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            unsigned long long* const a =
-                reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + c * NVOX * 8);
-            if constexpr (NONNEG && sizeof(T) == 4)
-              atomicAdd(a, to_fixed_nonneg((float)da, (float)wa[c]));
-            else
-              atomicAdd(a, to_fixed(da * wa[c]));
-          }
+        for (int c = 0; c < NCH; ++c) {
+          if constexpr (PK)
+            qv[c] = (uint32_t)fmaf((float)da, (float)wa[c], 0.5f);
+          else if constexpr (NONNEG && sizeof(T) == 4)
+            qv[c] = to_fixed_nonneg((float)da, (float)wa[c]);
+          else
+            qv[c] = to_fixed(da * wa[c]);
         }
       };
+      auto add = [&](int lb, const QT* qv) {
+        if constexpr (PK) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+            atomicAdd(reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + p * NVOX * 8),
+                      ((unsigned long long)qv[2 * p + 1] << 32) | qv[2 * p]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c)
+            atomicAdd(reinterpret_cast<unsigned long long*>(accb + (uint32_t)lb + c * NVOX * 8),
+                      (unsigned long long)qv[c]);
+        }
+      };
+      auto deposit = [&](int lb, T da) {
+        QT qv[NCH];
+        quant(da, qv);
+        add(lb, qv);
+      };
+      // a whole plane step inside one pixel, quantised once per ray: in a
+      // full step split between two pixels the second one receives this
+      // minus the first one's share (an exact integer split of the step)
+      QT LQ[NCH];
+      quant((T)1, LQ);
       const int q0 = ifloor(ry.alo) - la;        // first plane step (tile-relative)
       const int q1 = -ifloor(-ry.ahi) - la;      // one past the last
       T tp = ry.alo;                             // start of the current step
@@ -813,23 +830,28 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
         row8 += 8 * (C - tz0) * TXY;
       }
       uint32_t rest = 0;   // 3D: steps left to the general walk
-      for (int q = q0; q < q1; ++q) {
-        fa += (T)1;
-        const T tn = min_fin(fa, ry.ahi);
-        const T bn = fma(tn, ry.mb, ry.b0);
-        const int B = clampi(ifloor(bn), lbb, hb - 1);
-        bool flat = true;
+      // 3D: does the step ending at tn stay in the current slice?  If not,
+      // record it for the general walk and move to the new slice.
+      auto flat_step = [&](int q, T tn) {
         if constexpr (Z3) {
           const int D = ifloor(fma(tn, ry.mw, ry.w0));
           if (D != C) {
-            flat = false;
             rest |= 1u << q;
             const int C1 = clampi(D, tz0, tz1 - 1);
             row8 += 8 * (C1 - C) * TXY;
             C = C1;
+            return false;
           }
         }
-        if (flat) {
+        return true;
+      };
+      // a step that may be partial (the ray's first and last)
+      auto gstep = [&](int q) {
+        fa += (T)1;
+        const T tn = min_fin(fa, ry.ahi);
+        const T bn = fma(tn, ry.mb, ry.b0);
+        const int B = clampi(ifloor(bn), lbb, hb - 1);
+        if (flat_step(q, tn)) {
           const T ds = tn - tp;
           // the part of the step before the lateral crossing (all of it when
           // the step stays in one pixel)
@@ -841,6 +863,32 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
         A = B;
         tp = tn;
         bp = bn;
+      };
+      // a full step [fa, fa + 1]
+      auto fstep = [&](int q) {
+        fa += (T)1;
+        const T bn = fma(fa, ry.mb, ry.b0);
+        const int B = clampi(ifloor(bn), lbb, hb - 1);
+        if (flat_step(q, fa)) {
+          const T dA = (B == A) ? (T)1 : clamp0(((T)max(A, B) - bp) * ry.imb, (T)1);
+          QT qa[NCH];
+          quant(dA, qa);
+          add(__mul24(A, sb8) + row8, qa);
+          if (B != A) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) qa[c] = LQ[c] - qa[c];
+            add(__mul24(B, sb8) + row8, qa);
+          }
+        }
+        row8 += 8 * sa;
+        A = B;
+        bp = bn;
+      };
+      if (q0 < q1) {
+        gstep(q0);
+        for (int q = q0 + 1; q < q1 - 1; ++q) fstep(q);
+        tp = fa;   // the last step starts on a plane
+        if (q1 - 1 > q0) gstep(q1 - 1);
       }
       if constexpr (Z3) {
         const T iLa = (T)1 / ry.La;
