@@ -51,9 +51,6 @@ int check_plan(const deam_plan* p) {
   return DEAM_OK;
 }
 
-// Tile of the backprojector for `bpv` bytes of accumulators per voxel:
-// tz = min(nz, 64) slices and as many columns as fit in 80 KiB of LDS with
-// rows padded to tx + 1 words (capped at 16 x 16).
 // Upper bound of max_x sum_y h(x,y): per view at most nk channels and nr rows
 // pass through one voxel, each with a chord no longer than the voxel diagonal.
 double h1_bound(const deam_geometry& g) {
@@ -150,14 +147,22 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
     return o;
   };
   const size_t nblk = (size_t)p->fp_blocks;
+  // The packed image copies: natural order, then (with no gap) x-major order,
+  // then max(nx, ny)^2 zeroed elements.  The forward projector's lanes walk a
+  // common range of plane rows; a lane outside its own range reads, with zero
+  // weight, rows up to max(nx, ny) of its copy, which stay inside this region
+  // and hold finite values.
+  const size_t mx = (size_t)std::max(p->gd.nx, p->gd.ny);
+  auto take_packed = [&](size_t es) {
+    L.cp_y = take((2 * V + mx * mx) * es);
+    L.cp_x = L.cp_y + V * es;
+  };
   switch (op) {
     case DEAM_OP_FORWARD:
-      L.cp_y = take(V * 2 * rs);
-      L.cp_x = take(V * 2 * rs);
+      take_packed(2 * rs);
       break;
     case DEAM_OP_METAL_TRACE:
-      L.cp_y = take(V * 2 * 8);
-      L.cp_x = take(V * 2 * 8);
+      take_packed(2 * 8);
       break;
     case DEAM_OP_POLY_MEAN:
       L.partial = take(nblk * 8);
@@ -169,8 +174,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       break;
     case DEAM_OP_ITERATE:
     default:
-      L.cp_y = take(V * 2 * rs);
-      L.cp_x = take(V * 2 * rs);
+      take_packed(2 * rs);
       L.w = take(R * 4 * rs);
       L.b = take(V * 4 * rs);
       L.partial = take(nblk * 8);
@@ -198,9 +202,12 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   if (precision != DEAM_PREC_MIXED && precision != DEAM_PREC_FP64)
     return fail(DEAM_ERR_VALUE, "unknown precision %d", precision);
   {
-    // the projector addresses both packed image copies with 32-bit byte offsets
+    // the projector addresses both packed image copies (and the padding after
+    // the second) with 32-bit byte offsets; the metal trace packs in FP64 on
+    // every plan
     const double V = (double)geom->nx * geom->ny * (geom->kind == DEAM_HELICAL3D ? geom->nz : 1);
-    const double bytes = 2.0 * V * 2.0 * (precision == DEAM_PREC_FP64 ? 8.0 : 4.0) + 512.0;
+    const double mx = (double)std::max(geom->nx, geom->ny);
+    const double bytes = (2.0 * V + mx * mx) * 2.0 * 8.0 + 512.0;
     if (bytes >= 4294967296.0)
       return fail(DEAM_ERR_UNSUPPORTED, "volume too large for this build (packed images >= 4 GiB)");
   }

@@ -53,6 +53,13 @@ __device__ __forceinline__ int ifloor(double x) { return __double2int_rd(x); }
 // clamp to [0, hi] (v_med3_f32 for float)
 __device__ __forceinline__ float clamp0(float x, float hi) { return __builtin_amdgcn_fmed3f(x, 0.f, hi); }
 __device__ __forceinline__ double clamp0(double x, double hi) { return fmin(fmax(x, 0.0), hi); }
+// clamp to [lo, hi] (lo <= hi; v_med3_f32 for float)
+__device__ __forceinline__ float clampf(float x, float lo, float hi) {
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+__device__ __forceinline__ double clampf(double x, double lo, double hi) {
+  return fmin(fmax(x, lo), hi);
+}
 // min(x, hi) for finite operands, as the median of (x, hi, -3e38)
 // (v_med3_f32 for float: no canonicalisation of the loop-invariant bound
 // inside the loop)
@@ -217,7 +224,8 @@ __device__ __forceinline__ void neumaier(T& s, T& c, T x) {
 // in a 64-bit mask; every 16 groups (a point common to all lanes still
 // walking) and at the end, the recorded steps are summed through the general
 // walk_row.
-// Called by all lanes of the wave (valid = false: no ray, result 0).
+// Called by all lanes of the wave (valid = false: no ray, result 0); the
+// ray index runs fastest over the lanes.
 template <typename T, bool Z3>
 __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
                             const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff, int v,
@@ -246,42 +254,31 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   const int q1 = hit ? -ifloor(-ry.ahi) : -(1 << 30);
   T tp = ry.alo;                                         // start of the current step
   T bp = fma(tp, ry.mb, ry.b0);                          // lateral coordinate there
-  T fa = (T)q0;
   int A = clampi(ifloor(bp), 0, nb - 1);
   int C = 0;
-  // byte offset of lateral index 0 in the current plane row and slice
-  uint32_t row = (base + (uint32_t)q0 * (uint32_t)nb) * E;
-  if constexpr (Z3) {
-    C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), 0, nzz - 1);
-    row += (uint32_t)C * plane * E;
-  }
+  if constexpr (Z3) C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), 0, nzz - 1);
   uint64_t rest = 0;   // 3D: deferred steps, bit = step - qw
-  int qw = q0;
-  // one plane step: gather offsets and lengths (zero when deferred or when
-  // the step lies outside the ray's range, with a valid address)
+  int qw = 0;
+  T fa = 0;
+  uint32_t row = 0;   // byte offset of lateral index 0 in the current plane row and slice
+  // one plane step: gather offsets and lengths (zero when deferred)
   auto step = [&](int q, uint32_t& oA, uint32_t& oB, T& dA, T& dB) {
-    if (q < q0 || q >= q1) {
-      oA = 0u;
-      oB = 0u;
-      dA = (T)0;
-      dB = (T)0;
-      return;
-    }
     fa += (T)1;
-    const T tn = min_fin(fa, ry.ahi);
+    const T tn = clampf(fa, ry.alo, ry.ahi);
     const T bn = fma(tn, ry.mb, ry.b0);
     const int B = clampi(ifloor(bn), 0, nb - 1);
     T ds = tn - tp;
     const uint32_t rq = row;
     row += rstep;
     if constexpr (Z3) {
-      const int D = ifloor(fma(tn, ry.mw, ry.w0));
+      // (clamped: a step that reaches a face of the volume stays in the edge
+      // slice up to the ray's end)
+      const int D = clampi(ifloor(fma(tn, ry.mw, ry.w0)), 0, nzz - 1);
       if (D != C) {
         rest |= 1ull << (q - qw);
         ds = (T)0;
-        const int D1 = clampi(D, 0, nzz - 1);
-        row += (uint32_t)((D1 - C) * (int)plane) * E;
-        C = D1;
+        row += (uint32_t)((D - C) * (int)plane) * E;
+        C = D;
       }
     }
     const T a = (B == A) ? ds : clamp0(((T)max(A, B) - bp) * ry.imb, ds);
@@ -306,11 +303,15 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
       walk_row<T, true, false>(ry, qw + bit, 0, nb, 0, nzz, visit);
     }
   };
-  // the lanes of a wave walk the same plane rows together (a common range,
-  // lanes idle outside their own), so that their gathers share cache lines
+  // the lanes of a wave walk the same plane rows together (a common range),
+  // so that their gathers share cache lines; outside its own range a lane's
+  // steps have zero length (the step ends are clamped to [alo, ahi]) and its
+  // pixel state does not move
   const int qlo = wave_min(q0), qhi = wave_max(q1);
   if (qlo >= qhi) return;
   qw = qlo;
+  fa = (T)qlo;
+  row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)C * plane) * E;
   int q = qlo;
   int groups = 0;
   for (; q + 4 <= qhi; q += 4) {
@@ -1050,6 +1051,13 @@ hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8
     hipLaunchKernelGGL((k_pack<float, float>), image_grid(p), dim3(256), 0, st, p->gd,
                        (const float*)c, n_ch, (float2*)cp_y, (float2*)cp_x);
   }
+  // zero the padding after the x-major copy (which follows the natural copy
+  // with no gap): the forward projector reads it with zero weight, and 0 x NaN
+  // would not vanish
+  const size_t e2 = dbl ? sizeof(double2) : sizeof(float2);
+  const int64_t mx = max(p->gd.nx, p->gd.ny);
+  launch_fill_u32((uint32_t*)((char*)cp_x + (size_t)p->gd.V * e2), 0u,
+                  (int64_t)((size_t)mx * (size_t)mx * e2 / 4), st);
   return hipGetLastError();
 }
 
