@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--workload", default="fan512", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
