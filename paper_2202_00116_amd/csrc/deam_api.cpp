@@ -165,7 +165,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       take_packed(2 * 8);
       break;
     case DEAM_OP_POLY_MEAN:
-      L.partial = take(nblk * 8);
+      L.partial = take((size_t)p->ray_blocks * 8);
       L.wmax = take(64);
       L.scratch = take(64);
       break;
@@ -351,7 +351,13 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
 
   p->h1_bound = h1_bound(g);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
-  p->fp_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
+  p->ray_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
+  if (g.kind == DEAM_HELICAL3D) {
+    const int rg = precision == DEAM_PREC_FP64 ? deam::fp3_rows<double>() : deam::fp3_rows<float>();
+    p->fp_blocks = deam::fp3_blocks(g.n_views, g.n_rows, g.n_cols, rg);
+  } else {
+    p->fp_blocks = p->ray_blocks;
+  }
   *out = p;
   return ok();
 }
@@ -438,10 +444,7 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
   double* partial = (double*)(wsb + L.partial);
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
   HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
-  if (obj) {
-    const int64_t nb = (plan->gd.R + deam::kFpBlock - 1) / deam::kFpBlock;
-    HIP_TRY(deam::launch_reduce(partial, nb, obj, st));
-  }
+  if (obj) HIP_TRY(deam::launch_reduce(partial, plan->ray_blocks, obj, st));
   return ok();
 }
 
@@ -514,8 +517,9 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
       return fail(DEAM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));                   \
     }                                                                                      \
   } while (0)
-  // projection copies of the starting image
+  // projection copies of the starting image, and the zeroed tail after them
   STEP(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
+  STEP(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
     STEP(deam::launch_fill_u32(wmax, 0u, 16, st));
     STEP(mark(k, 0));

@@ -79,6 +79,18 @@ struct BpTile {
 enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
 
 constexpr int kFpBlock = 256;
+
+// 3D projector: detector rows walked together by one lane (see k_fp3), and
+// its grid: (view, row group, channel padded to whole waves)
+template <typename T>
+constexpr int fp3_rows() { return sizeof(T) == 4 ? 4 : 2; }
+constexpr int kFp3Views = 4;   // consecutive views per block (one wave each)
+inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
+  const int64_t nkb = (n_cols + 63) / 64;                       // channel blocks of 64
+  const int64_t nvb = (n_views + kFp3Views - 1) / kFp3Views;    // view blocks
+  const int64_t ng = (n_rows + rg - 1) / rg;
+  return nvb * nkb * ng;
+}
 constexpr int kViewBatch = 32;
 
 // Workspace pieces (byte offsets, 256-aligned).
@@ -106,7 +118,8 @@ struct deam_plan {
   void* d_energy;                // EBin<float> or EBin<double> [nE]
   double h1_bound;               // upper bound of max_x sum_y h(x,y)
   double hmax;                   // upper bound of one h(x,y): the voxel diagonal
-  int64_t fp_blocks;             // blocks of the ray kernels
+  int64_t fp_blocks;             // blocks of the fused projector kernel (its FP64 partials)
+  int64_t ray_blocks;            // blocks of one-thread-per-ray kernels
 };
 
 namespace deam {
@@ -114,6 +127,7 @@ namespace deam {
 // Launchers (deam_kernels.hip).  All asynchronous on `st`.
 hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8, bool dbl,
                        void* cp_y, void* cp_x, hipStream_t st);
+hipError_t launch_zero_tail(const deam_plan* p, void* cp_x, bool dbl, hipStream_t st);
 hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
                           int n_out, hipStream_t st);
 hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* cp_x, double t,

@@ -463,11 +463,11 @@ __device__ void poly_epilogue(const EBin<T>* __restrict__ eb, int nE, T l1, T l2
 
 // Block reductions: FP64 sum into partial[lb], float max into wmax (atomicMax
 // on the bit pattern, valid for non-negative values).
-template <int NW>
+template <int NW, int NT = kFpBlock>
 __device__ void block_reduce(double term, const float wabs[4], int nch, double* partial, int lb,
                              uint32_t* wmax) {
-  __shared__ double s_sum[kFpBlock / 64];
-  __shared__ float s_max[kFpBlock / 64][4];
+  __shared__ double s_sum[NT / 64];
+  __shared__ float s_max[NT / 64][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float m[4] = {wabs[0], wabs[1], wabs[2], wabs[3]};
 #pragma unroll
@@ -484,7 +484,7 @@ __device__ void block_reduce(double term, const float wabs[4], int nch, double* 
   if (threadIdx.x == 0) {
     double s = 0.0;
     float mm[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int i = 0; i < kFpBlock / 64; ++i) {
+    for (int i = 0; i < NT / 64; ++i) {
       s += s_sum[i];
       for (int c = 0; c < 4; ++c) mm[c] = fmaxf(mm[c], s_max[i][c]);
     }
@@ -532,6 +532,254 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
   if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
     const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
     block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax);
+  }
+}
+
+// 3D projector.  The detector rows of one (view, channel) share the in-plane
+// path of their rays and differ only in z, so one lane walks the in-plane
+// path of a (view, channel) once and gathers RG rows at every plane step:
+// the lateral geometry of a step (pixels, split, lengths, gather offsets) is
+// computed once for RG line integrals, and each row only finds its slice.
+// A wave holds 64 neighbouring channels of one (view, row group), so the
+// rows' axial slopes are wave-uniform; the waves of a block take
+// consecutive views of the same channels and rows, whose rays lie within
+// about a pixel of each other, so that they gather through the same cache
+// lines.  Blocks run over the views, then the channel blocks, then the row
+// groups.  The lanes of a wave walk the same plane rows together, as in
+// project_ray.
+// Row j's axial grid coordinate is w_j(a) = w_s + (a - s_a) / d_a * zr_j
+// (zr_j = zeta_j / dz); its slice for a step is that of the step's end.  A
+// row outside the slices gathers from the zeroed tail of the packed images.
+// A step in which a row changes slice is gathered from the new slice by the
+// fast walk, recorded in a mask, and corrected later: the exact pieces are
+// summed through the general walker and the fast walk's value (recomputed
+// with identical arithmetic) is taken away.
+template <typename T, int MODE, int RG>
+__global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
+    GeomDev G, const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff,
+    const EBin<T>* __restrict__ eb, int nE,
+    const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
+    double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
+    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
+  using T2 = typename Vec2<T>::type;
+  constexpr uint32_t E = sizeof(T2);
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int NKB = (G.n_cols + 63) >> 6;                           // channel blocks of 64
+  const int NVB = (G.n_views + kFp3Views - 1) / kFp3Views;        // view blocks
+  const int vb = lb % NVB, kb = (lb / NVB) % NKB, g = lb / (NVB * NKB);
+  const int v = vb * kFp3Views + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int k = kb * 64 + (int)(threadIdx.x & 63);
+  const bool valid = v < G.n_views && k < G.n_cols;
+  const int r0 = g * RG;
+  const RayXY<T>* __restrict__ rays =
+      (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
+  RayXY<T> t{};
+  if (valid) t = rays[(int64_t)v * G.n_cols + k];
+  const bool yd = t.yd != (T)0;
+  const int nb = yd ? G.nx : G.ny, na = yd ? G.ny : G.nx;
+  const uint32_t base = yd ? 0u : xoff;
+  const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
+  const uint32_t pstep = plane * E, rstep = (uint32_t)nb * E;
+  // offset from a lane's in-plane address to the zeroed tail after both copies
+  const uint32_t zoff0 = (2u * (uint32_t)G.V - base) * E;
+  const int vs = min(v, G.n_views - 1);
+  const T sw = (T)G.view[4 * vs + 3];
+  T zr[RG], Lr[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int r = min(r0 + j, G.n_rows - 1);
+    zr[j] = (T)G.row[4 * r];
+    Lr[j] = (T)G.row[4 * r + 1];
+  }
+  // in-plane clip to the x-y extent of the grid
+  T alo = 0, ahi = (T)na;
+  bool hit = valid;
+  if (t.mb != (T)0) {
+    const T t0 = ((T)0 - t.b0) * t.imb, t1 = ((T)nb - t.b0) * t.imb;
+    alo = fmax(alo, fmin(t0, t1));
+    ahi = fmin(ahi, fmax(t0, t1));
+  } else if (!(t.b0 >= (T)0 && t.b0 < (T)nb)) {
+    hit = false;
+  }
+  hit = hit && ahi > alo;
+  if (!hit) {
+    alo = 0;
+    ahi = 0;
+  }
+  const int nzz = G.nz;
+  auto slice_off = [&](int D) -> uint32_t {
+    return (D >= 0 && D < nzz) ? (uint32_t)D * pstep : zoff0;
+  };
+  const char* __restrict__ cpb = (const char*)cp;
+  T s1[RG], c1[RG], s2[RG], c2[RG], p1[RG], p2[RG];
+  int C[RG];
+  uint32_t zo[RG], rest[RG];
+  T tp = alo;
+  T bp = fma(tp, t.mb, t.b0);
+  int A = clampi(ifloor(bp), 0, nb - 1);
+  {
+    const T u = (tp - t.sa) * t.ida;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      s1[j] = c1[j] = s2[j] = c2[j] = p1[j] = p2[j] = 0;
+      C[j] = ifloor(fma(u, zr[j], sw));
+      zo[j] = slice_off(C[j]);
+      rest[j] = 0u;
+    }
+  }
+  const int q0 = hit ? ifloor(alo) : (1 << 30);
+  const int q1 = hit ? -ifloor(-ahi) : -(1 << 30);
+  const int qlo = wave_min(q0), qhi = wave_max(q1);
+  T iLa[RG];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) iLa[j] = (T)1 / (Lr[j] * fabs(t.ida));
+
+  if (qlo < qhi) {
+    T fa = (T)qlo;
+    uint32_t row = (base + (uint32_t)qlo * (uint32_t)nb) * E;
+    int qw = qlo;
+    // the fast walk's lengths and offsets of plane step q (identical
+    // arithmetic to the walk itself)
+    auto step_geom = [&](int q, T& dA, T& dB, uint32_t& oA, uint32_t& oB, T& tn) {
+      const T ta = clampf((T)q, alo, ahi);
+      tn = clampf((T)(q + 1), alo, ahi);
+      const T ba = fma(ta, t.mb, t.b0), bn = fma(tn, t.mb, t.b0);
+      const int Aq = clampi(ifloor(ba), 0, nb - 1), Bq = clampi(ifloor(bn), 0, nb - 1);
+      const T ds = tn - ta;
+      dA = (Bq == Aq) ? ds : clamp0(((T)max(Aq, Bq) - ba) * t.imb, ds);
+      dB = ds - dA;
+      const uint32_t rq = (base + (uint32_t)q * (uint32_t)nb) * E;
+      oA = rq + (uint32_t)Aq * E;
+      oB = rq + (uint32_t)Bq * E;
+    };
+    auto fixup = [&]() {
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        if (rest[j] == 0u) continue;
+        // row j's ray clipped to the whole grid
+        Ray<T> ry{};
+        ry.b0 = t.b0;
+        ry.mb = t.mb;
+        ry.imb = t.imb;
+        ry.mw = zr[j] * t.ida;
+        ry.w0 = sw - t.sa * ry.mw;
+        const T rmw = ry.mw != (T)0 ? (T)1 / ry.mw : (T)0;
+        ry.imw = fabs(rmw);
+        ry.La = Lr[j] * fabs(t.ida);
+        ry.Lb = Lr[j] * t.iadb;
+        ry.alo = alo;
+        ry.ahi = ahi;
+        ry.ydrive = yd ? 1 : 0;
+        if (ry.mw != (T)0) {
+          const T z0 = ((T)0 - ry.w0) * rmw, z1 = ((T)nzz - ry.w0) * rmw;
+          ry.alo = fmax(ry.alo, fmin(z0, z1));
+          ry.ahi = fmin(ry.ahi, fmax(z0, z1));
+        } else if (!(ry.w0 >= (T)0 && ry.w0 < (T)nzz)) {
+          ry.ahi = ry.alo;
+        }
+        T e1 = 0, e2 = 0;
+        auto visit = [&](int ia, int ib, int iw, T h) {
+          const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
+          e1 = fma(h * iLa[j], cv.x, e1);
+          e2 = fma(h * iLa[j], cv.y, e2);
+        };
+        while (rest[j] != 0u) {
+          const int bit = __ffs(rest[j]) - 1;
+          rest[j] &= rest[j] - 1u;
+          const int q = qw + bit;
+          T dA, dB, tn;
+          uint32_t oA, oB;
+          step_geom(q, dA, dB, oA, oB, tn);
+          const uint32_t z = slice_off(ifloor(fma((tn - t.sa) * t.ida, zr[j], sw)));
+          const T2 vA = *(const T2*)(cpb + oA + z), vB = *(const T2*)(cpb + oB + z);
+          e1 -= fma(dA, vA.x, dB * vB.x);
+          e2 -= fma(dA, vA.y, dB * vB.y);
+          walk_row<T, true, false>(ry, q, 0, nb, 0, nzz, visit);
+        }
+        p1[j] += e1;
+        p2[j] += e2;
+      }
+    };
+    int nstep = 0;
+    for (int q = qlo; q < qhi; ++q) {
+      fa += (T)1;
+      const T tn = clampf(fa, alo, ahi);
+      const T bn = fma(tn, t.mb, t.b0);
+      const int B = clampi(ifloor(bn), 0, nb - 1);
+      const T ds = tn - tp;
+      const T dA = (B == A) ? ds : clamp0(((T)max(A, B) - bp) * t.imb, ds);
+      const T dB = ds - dA;
+      const uint32_t oA = row + (uint32_t)A * E, oB = row + (uint32_t)B * E;
+      row += rstep;
+      const T un = (tn - t.sa) * t.ida;
+      T2 vA[RG], vB[RG];
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        const int D = ifloor(fma(un, zr[j], sw));
+        if (D != C[j]) {
+          rest[j] |= 1u << (q - qw);
+          C[j] = D;
+          zo[j] = slice_off(D);
+        }
+        vA[j] = *(const T2*)(cpb + oA + zo[j]);
+        vB[j] = *(const T2*)(cpb + oB + zo[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        p1[j] = fma(dA, vA[j].x, fma(dB, vB[j].x, p1[j]));
+        p2[j] = fma(dA, vA[j].y, fma(dB, vB[j].y, p2[j]));
+      }
+      A = B;
+      bp = bn;
+      tp = tn;
+      ++nstep;
+      if ((nstep & 15) == 0) {
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+          neumaier(s1[j], c1[j], p1[j]);
+          neumaier(s2[j], c2[j], p2[j]);
+          p1[j] = 0;
+          p2[j] = 0;
+        }
+      }
+      if ((nstep & 31) == 0) {
+        fixup();
+        qw = q + 1;
+      }
+    }
+    fixup();
+  }
+
+  double term = 0.0;
+  T wabs[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    neumaier(s1[j], c1[j], p1[j]);
+    neumaier(s2[j], c2[j], p2[j]);
+    const int r = r0 + j;
+    if (!valid || r >= G.n_rows) continue;
+    const T La = Lr[j] * fabs(t.ida);
+    const T l1 = hit ? (s1[j] + c1[j]) * La : (T)0;
+    const T l2 = hit ? (s2[j] + c2[j]) * La : (T)0;
+    const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
+    if constexpr (MODE == PM_L) {
+      out[ray] = l1;
+      if (nout > 1) out[G.R + ray] = l2;
+    } else if constexpr (MODE == PM_TRACE) {
+      if (Tout) Tout[ray] = (double)l1;
+      mask_out[ray] = (double)l1 >= tthr ? 1 : 0;
+    } else {
+      double tj = 0.0;
+      T wj[4] = {0, 0, 0, 0};
+      poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, tj, wj);
+      term += tj;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) wabs[c] = fmax(wabs[c], wj[c]);
+    }
+  }
+  if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
+    const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
+    block_reduce<4, 64 * kFp3Views>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax);
   }
 }
 
@@ -1051,14 +1299,20 @@ hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8
     hipLaunchKernelGGL((k_pack<float, float>), image_grid(p), dim3(256), 0, st, p->gd,
                        (const float*)c, n_ch, (float2*)cp_y, (float2*)cp_x);
   }
-  // zero the padding after the x-major copy (which follows the natural copy
-  // with no gap): the forward projector reads it with zero weight, and 0 x NaN
-  // would not vanish
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_zero_tail(p, cp_x, dbl, st);
+}
+
+// Zero the max(nx,ny)^2 elements after the x-major copy (which follows the
+// natural copy with no gap): the forward projectors read them for rays
+// outside the slices and for idle lanes, so they must hold zeros (0 x NaN
+// would not vanish).
+hipError_t launch_zero_tail(const deam_plan* p, void* cp_x, bool dbl, hipStream_t st) {
   const size_t e2 = dbl ? sizeof(double2) : sizeof(float2);
   const int64_t mx = max(p->gd.nx, p->gd.ny);
-  launch_fill_u32((uint32_t*)((char*)cp_x + (size_t)p->gd.V * e2), 0u,
-                  (int64_t)((size_t)mx * (size_t)mx * e2 / 4), st);
-  return hipGetLastError();
+  return launch_fill_u32((uint32_t*)((char*)cp_x + (size_t)p->gd.V * e2), 0u,
+                         (int64_t)((size_t)mx * (size_t)mx * e2 / 4), st);
 }
 
 template <typename T, int MODE>
@@ -1066,14 +1320,17 @@ static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, 
                         const uint8_t* mask, void* out, double* partial, uint32_t* wmax,
                         double tthr, uint8_t* mask_out, double* Tout, hipStream_t st, int nout = 2) {
   using T2 = typename Vec2<T>::type;
-  const dim3 grid((unsigned)p->fp_blocks), blk(kFpBlock);
+  const dim3 grid((unsigned)p->ray_blocks), blk(kFpBlock);
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
   // the x-major copy follows the natural one in the same allocation
   const uint32_t xoff = (uint32_t)(((const T2*)cp_x) - ((const T2*)cp_y));
-  if (p->gd.is3d)
-    hipLaunchKernelGGL((k_fp<T, true, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
+  if (p->gd.is3d) {
+    constexpr int RG = fp3_rows<T>();
+    const dim3 grid3((unsigned)fp3_blocks(p->gd.n_views, p->gd.n_rows, p->gd.n_cols, RG));
+    hipLaunchKernelGGL((k_fp3<T, MODE, RG>), grid3, dim3(64 * kFp3Views), 0, st, p->gd,
+                       (const T2*)cp_y, xoff,
                        eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
-  else
+  } else
     hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
                        eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
 }
