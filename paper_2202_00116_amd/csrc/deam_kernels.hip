@@ -864,6 +864,77 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
   return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
 }
 
+// View set-up of a tile for one batch of kViewBatch views (all threads of
+// the block take part; two barriers).  For every view of the batch: the
+// channels [kl, kl + nk) whose rays can meet the tile, from the channel
+// coordinates of the tile's corners, and the detector rows [rl, rl + nr)
+// whose rays can meet its slices, from its z-range and its distance to the
+// source; s_off receives the exclusive prefix sum of the work items per view,
+// nk * ceil(nr / RG).
+template <int RG>
+__device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0, double X1,
+                                           double Y0, double Y1, double Z0, double Z1,
+                                           float (*s_kap)[4], int* s_kl, int* s_nk, int* s_rl,
+                                           int* s_nr, int* s_off) {
+  if (threadIdx.x < 4 * kViewBatch) {
+    const int j = threadIdx.x >> 2, cn = threadIdx.x & 3;
+    const int v = vb0 + j;
+    float kap = 0.f;
+    if (v < G.n_views) {
+      const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
+      const double px = (cn & 1) ? X1 : X0, py = (cn & 2) ? Y1 : Y0;
+      const double qx = px - G.sid * cb, qy = py - G.sid * sb;
+      const float cr = (float)(-cb * qy + sb * qx), dt = (float)(-cb * qx - sb * qy);
+      kap = atan2f(cr, dt) / (float)G.dgamma + (float)G.kc;
+    }
+    s_kap[j][cn] = kap;
+  }
+  __syncthreads();
+  // channel and row ranges of each view and their prefix sum (one wave)
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x, v = vb0 + j;
+    int kl = 0, nk = 0, rl = 0, nr = 0;
+    if (j < kViewBatch && v < G.n_views) {
+      const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
+      const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
+      kl = max((int)ceilf(kmn - 0.01f), 0);
+      const int kh = min((int)floorf(kmx + 0.01f), G.n_cols - 1);
+      nk = max(kh - kl + 1, 0);
+      if (G.is3d) {
+        const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
+        const double zs = G.view[4 * v + 2];
+        const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
+        const double dmin = fmax(sqrt((sx - cx) * (sx - cx) + (sy - cy) * (sy - cy)), 1e-6);
+        const double fx = fmax(fabs(sx - X0), fabs(sx - X1)), fy = fmax(fabs(sy - Y0), fabs(sy - Y1));
+        const double dmax = sqrt(fx * fx + fy * fy);
+        const double za = (Z0 - zs) * G.sdd, zb = (Z1 - zs) * G.sdd;
+        const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
+        const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
+        rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
+        const int rh = min(ifloor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
+        nr = max(rh - rl + 1, 0);
+      } else {
+        nr = 1;
+      }
+    }
+    int run = nk * ((nr + RG - 1) / RG);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(run, d);
+      if (j >= d) run += u;
+    }
+    if (j < kViewBatch) {
+      s_kl[j] = kl;
+      s_nk[j] = nk;
+      s_rl[j] = rl;
+      s_nr[j] = nr;
+      s_off[j + 1] = run;
+    }
+    if (j == 0) s_off[0] = 0;
+  }
+  __syncthreads();
+}
+
 // One backprojector for both geometries.  A workgroup owns a tile of
 // BpTile<Z3, NCH> voxels in LDS and scatters every ray that meets it, view
 // batch by view batch; work items are (view, detector row, channel) with the
@@ -898,7 +969,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
   static_assert(BT::tx <= 32 && BT::ty <= 32, "deferred steps live in a 32-bit mask");
   extern __shared__ unsigned long long acc[];
   __shared__ float s_kap[kViewBatch][4];
-  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch];
+  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_nr[kViewBatch];
   __shared__ int s_off[kViewBatch + 1];
   const RayXY<T>* __restrict__ rays =
       (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
@@ -943,65 +1014,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
   __syncthreads();
 
   for (int vb0 = 0; vb0 < G.n_views; vb0 += kViewBatch) {
-    // channel coordinate of the 4 tile corners for each view of the batch
-    if (threadIdx.x < 4 * kViewBatch) {
-      const int j = threadIdx.x >> 2, cn = threadIdx.x & 3;
-      const int v = vb0 + j;
-      float kap = 0.f;
-      if (v < G.n_views) {
-        const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
-        const double px = (cn & 1) ? X1 : X0, py = (cn & 2) ? Y1 : Y0;
-        const double qx = px - G.sid * cb, qy = py - G.sid * sb;
-        const float cr = (float)(-cb * qy + sb * qx), dt = (float)(-cb * qx - sb * qy);
-        kap = atan2f(cr, dt) / (float)G.dgamma + (float)G.kc;
-      }
-      s_kap[j][cn] = kap;
-    }
-    __syncthreads();
-    // channel and row ranges of each view, and their exclusive prefix sum
-    // (one wave)
-    if (threadIdx.x < 64) {
-      const int j = threadIdx.x, v = vb0 + j;
-      int kl = 0, nk = 0, rl = 0, nr = 0;
-      if (j < kViewBatch && v < G.n_views) {
-        const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
-        const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
-        kl = max((int)ceilf(kmn - 0.01f), 0);
-        const int kh = min((int)floorf(kmx + 0.01f), G.n_cols - 1);
-        nk = max(kh - kl + 1, 0);
-        if (G.is3d) {
-          // detector rows whose rays can meet the tile's slices
-          const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
-          const double zs = G.view[4 * v + 2];
-          const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
-          const double dmin = fmax(sqrt((sx - cx) * (sx - cx) + (sy - cy) * (sy - cy)), 1e-6);
-          const double fx = fmax(fabs(sx - X0), fabs(sx - X1)), fy = fmax(fabs(sy - Y0), fabs(sy - Y1));
-          const double dmax = sqrt(fx * fx + fy * fy);
-          const double za = (Z0 - zs) * G.sdd, zb = (Z1 - zs) * G.sdd;
-          const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
-          const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
-          rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
-          const int rh = min(ifloor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
-          nr = max(rh - rl + 1, 0);
-        } else {
-          nr = 1;
-        }
-      }
-      int run = nk * nr;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(run, d);
-        if (j >= d) run += u;
-      }
-      if (j < kViewBatch) {
-        s_kl[j] = kl;
-        s_nk[j] = nk;
-        s_rl[j] = rl;
-        s_off[j + 1] = run;
-      }
-      if (j == 0) s_off[0] = 0;
-    }
-    __syncthreads();
+    cull_views<1>(G, vb0, X0, X1, Y0, Y1, Z0, Z1, s_kap, s_kl, s_nk, s_rl, s_nr, s_off);
     const int total = s_off[kViewBatch];
     for (int it = threadIdx.x; it < total; it += NT) {
       // view of the item: the last j with s_off[j] <= it (binary search)
