@@ -275,6 +275,7 @@ void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
     double l1 = l[y], l2 = l[R + y];
     nsum gs[2] = {{0, 0}, {0, 0}};
     nsum as[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};   /* as[i][j] */
+    nsum ms[2][3] = {{{0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}}};  /* m_11, m_12, m_22 */
     for (int e = 0; e < nE; ++e) {
       double mu1 = mu[e], mu2 = mu[nE + e];
       double ex = exp(-(mu1 * l1 + mu2 * l2));
@@ -283,6 +284,11 @@ void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
         nadd(&gs[j], q);
         nadd(&as[0][j], mu1 * q);
         nadd(&as[1][j], mu2 * q);
+        if (mode == ORC_W_STEP_VJP) {                       /* sum_E mu_i mu_k q_j */
+          nadd(&ms[j][0], mu1 * mu1 * q);
+          nadd(&ms[j][1], mu1 * mu2 * q);
+          nadd(&ms[j][2], mu2 * mu2 * q);
+        }
       }
     }
     double gj[2] = {nval(&gs[0]), nval(&gs[1])};
@@ -317,9 +323,41 @@ void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
           if (!(g > 0.0)) continue;
           term += g - (dj > 0.0 ? dj * log(g) : 0.0);
         }
-    } else { /* ORC_W_VJP: u_i = -sum_j v_j a_ij, with v_j = dloss/dg_j */
+    } else if (mode == ORC_W_VJP) { /* u_i = -sum_j v_j a_ij, with v_j = dloss/dg_j */
       for (int i = 0; i < 2; ++i)
         w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][1]);
+    } else { /* ORC_W_STEP_VJP */
+      /* Upstream gradients alpha_i = dloss/dw~_i and beta_i = dloss/dw^_i (v =
+       * [alpha_1, alpha_2, beta_1, beta_2]); output lambda_k = dloss/dl_k.
+       * With dq_j/dl_k = -mu_k q_j: dg_j/dl_k = -a_kj, da_ij/dl_k = -m_ik^j,
+       * d(d_j/g_j)/dl_k = (d_j/g_j^2) a_kj off the trace (r_j = 1 and
+       * constant on it; r_j a_ij := 0 when g_j = 0), so
+       *   dw~_i/dl_k = sum_j [ (d_j/g_j^2) a_kj a_ij - r_j m_ik^j ]
+       *   dw^_i/dl_k = -sum_j m_ik^j.                                        */
+      double m[2][2][2];   /* m[j][i][k] */
+      for (int j = 0; j < 2; ++j) {
+        m[j][0][0] = nval(&ms[j][0]);
+        m[j][0][1] = m[j][1][0] = nval(&ms[j][1]);
+        m[j][1][1] = nval(&ms[j][2]);
+      }
+      for (int k = 0; k < 2; ++k) {
+        double lam = 0.0;
+        for (int i = 0; i < 2; ++i) {
+          double al = v[(long)i * R + y], be = v[(long)(2 + i) * R + y];
+          double dwt = 0.0, dwh = 0.0;
+          for (int j = 0; j < 2; ++j) {
+            double dj = d[(long)j * R + y], g = gj[j];
+            double r;
+            if (metal) r = 1.0;
+            else r = g > 0.0 ? dj / g : 0.0;
+            if (!metal && g > 0.0) dwt += dj / (g * g) * a[k][j] * a[i][j];
+            if (metal || g > 0.0) dwt -= r * m[j][i][k];
+            dwh -= m[j][i][k];
+          }
+          lam += al * dwt + be * dwh;
+        }
+        w[(long)k * R + y] = lam;
+      }
     }
     if (gout) { gout[y] = gj[0]; gout[R + y] = gj[1]; }
     if (obj) obj[y] = term;
@@ -382,6 +420,44 @@ int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
     orc_update(V, b, Z, c);
   }
   free(l); free(w); free(obj); free(b);
+  return 0;
+}
+
+/* Vector-Jacobian product of one DEAM iteration Phi(c) = c - ln(b~/b^)/Z
+ * (componentwise, c unchanged where b~ <= 0 or b^ <= 0): out = G + H^T lambda
+ * for the upstream gradient G = dloss/dPhi (both [2][V]), with
+ *   u~_i = -G_i / (Z_i b~_i), u^_i = G_i / (Z_i b^_i)    (0 where skipped)
+ *   alpha = H u~, beta = H u^, lambda from the STEP_VJP poly-mean mode.     */
+int orc_step_vjp(const orc_geom* g, int nE, const double* I0, const double* mu,
+                 const double* d, const unsigned char* mask, const double Z[2],
+                 const double* c, const double* G, double* out) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* b = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  double* u = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  double* ab = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* lam = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  if (!l || !w || !b || !u || !ab || !lam) {
+    free(l); free(w); free(b); free(u); free(ab); free(lam);
+    return -1;
+  }
+  orc_forward(g, 2, c, l);
+  orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_AM, NULL, w, NULL, NULL);
+  orc_backproject(g, 4, w, b);
+  for (int i = 0; i < 2; ++i)
+    for (long x = 0; x < V; ++x) {
+      double bt = b[(long)i * V + x], bh = b[(long)(2 + i) * V + x];
+      double gi = G[(long)i * V + x];
+      int act = bt > 0.0 && bh > 0.0;
+      u[(long)i * V + x] = act ? -gi / (Z[i] * bt) : 0.0;       /* dloss/db~_i */
+      u[(long)(2 + i) * V + x] = act ? gi / (Z[i] * bh) : 0.0;  /* dloss/db^_i */
+    }
+  orc_forward(g, 4, u, ab);
+  orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_STEP_VJP, ab, lam, NULL, NULL);
+  orc_backproject(g, 2, lam, out);
+  for (long x = 0; x < 2 * V; ++x) out[x] += G[x];
+  free(l); free(w); free(b); free(u); free(ab); free(lam);
   return 0;
 }
 

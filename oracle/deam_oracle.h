@@ -10,7 +10,7 @@ extern "C" {
 #endif
 
 enum { ORC_FAN2D = 0, ORC_HELICAL3D = 1 };
-enum { ORC_W_AM = 0, ORC_W_GRAD = 1, ORC_W_VJP = 2 };
+enum { ORC_W_AM = 0, ORC_W_GRAD = 1, ORC_W_VJP = 2, ORC_W_STEP_VJP = 3 };
 
 typedef struct {
   int kind, nx, ny, nz;
@@ -36,6 +36,9 @@ void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
                    const double* l, const double* d, const unsigned char* mask,
                    int mode, const double* v, double* w, double* gout, double* obj);
 double orc_sum(long n, const double* x);
+int orc_step_vjp(const orc_geom* g, int nE, const double* I0, const double* mu,
+                 const double* d, const unsigned char* mask, const double Z[2],
+                 const double* c, const double* G, double* out);
 void orc_update(long V, const double* b, const double Z[2], double* c);
 void orc_metal_trace(const orc_geom* g, const unsigned char* M, double t,
                      unsigned char* mask, double* T);

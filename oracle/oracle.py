@@ -10,6 +10,8 @@ Each function mirrors one step of the DEAM hot path:
                  (Eq. 8; Eqs. 9-10; Eq. 11 substitution p = q on the trace)
     update       c_i <- c_i - ln(b~_i / b^_i) / Z_i
     iterate      the DEAM loop with the masked I-divergence history (Eq. 5)
+    step_vjp     vector-Jacobian product of one iteration (chain rule through
+                 the update, the backprojection, the weights and Eq. 8)
     metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
 """
 from __future__ import annotations
@@ -24,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-W_AM, W_GRAD, W_VJP = 0, 1, 2
+W_AM, W_GRAD, W_VJP, W_STEP_VJP = 0, 1, 2, 3
 
 
 class OrcGeom(C.Structure):
@@ -107,6 +109,8 @@ def _setup(L):
     L.orc_objective.restype = C.c_double
     L.orc_nll_grad.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_void_p]
     L.orc_nll_grad.restype = C.c_double
+    L.orc_step_vjp.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, d1, d1, C.c_void_p]
+    L.orc_step_vjp.restype = C.c_int
     return L
 
 
@@ -176,6 +180,9 @@ def poly_mean(I0, mu, l, d, mask=None, mode=W_AM, v=None):
     mode W_AM  : w (4, R) = (w~1, w~2, w^1, w^2); obj = masked I-divergence terms
     mode W_GRAD: w (2, R) = u_i = sum_j (r_j - 1) a_ij; obj = NLL terms g - d ln g
     mode W_VJP : w (2, R) = -sum_j v_j a_ij
+    mode W_STEP_VJP: v (4, R) = (dloss/dw~_1, dloss/dw~_2, dloss/dw^_1, dloss/dw^_2);
+                 w (2, R) = dloss/dl_k (chain rule through g, a and the
+                 second moments sum_E mu_i mu_k q_j)
     """
     I0, mu, l, d = _f64(I0), _f64(mu), _f64(l), _f64(d)
     R = l.shape[-1]
@@ -223,6 +230,20 @@ def iterate(g, I0, mu, d, mask, Z, c0, n_iter):
     if rc != 0:
         raise MemoryError("oracle iterate allocation failed")
     return c, hist[:n_iter]
+
+
+def step_vjp(g, I0, mu, d, mask, Z, c, G):
+    """Vector-Jacobian product of one DEAM iteration c -> c - ln(b~/b^)/Z at c
+    for the upstream gradient G (both (2, V)): G + H^T lambda."""
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    out = np.zeros(2 * g.n_voxels)
+    rc = lib().orc_step_vjp(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                            _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
+                            _f64(c).reshape(-1), _f64(G).reshape(-1),
+                            out.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle step_vjp allocation failed")
+    return out.reshape(2, g.n_voxels)
 
 
 def objective(g, I0, mu, d, mask, c, mode=W_AM):

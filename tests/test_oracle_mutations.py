@@ -10,6 +10,7 @@ import pytest
 
 import tests.test_oracle_deam as D
 import tests.test_oracle_geometry as Gm
+import tests.test_oracle_unrolled as U
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "deam_oracle.c")
@@ -40,6 +41,13 @@ MUTATIONS = {
                          "w[(long)i * R + y] = (ra[i][0] - a[i][0]) - (ra[i][1] - a[i][1]);"),
     "ray_length_2d": ("double L = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);",
                       "double L = sqrt(D[0] * D[0] + D[1] * D[1]);"),
+    "step_vjp_ratio_term": ("if (!metal && g > 0.0) dwt += dj / (g * g) * a[k][j] * a[i][j];",
+                            "if (!metal && g > 0.0) dwt -= dj / (g * g) * a[k][j] * a[i][j];"),
+    "step_vjp_moment_index": ("if (metal || g > 0.0) dwt -= r * m[j][i][k];",
+                              "if (metal || g > 0.0) dwt -= r * m[j][i][i];"),
+    "step_vjp_hat_sign": ("dwh -= m[j][i][k];", "dwh += m[j][i][k];"),
+    "step_vjp_upstream_sign": ("u[(long)i * V + x] = act ? -gi / (Z[i] * bt) : 0.0;",
+                               "u[(long)i * V + x] = act ? gi / (Z[i] * bt) : 0.0;"),
 }
 
 PINS = [
@@ -59,6 +67,7 @@ PINS = [
     lambda o: D.test_monoenergetic_matches_textbook_am(o),
     lambda o: D.test_masked_idiv_nonincreasing(o, "fan64", 20, True),
     lambda o: D.test_gradient_matches_finite_differences(o),
+    lambda o: U.test_step_vjp_matches_finite_differences(o),
 ]
 
 
