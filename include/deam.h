@@ -71,7 +71,9 @@ typedef enum { DEAM_PREC_MIXED = 0, DEAM_PREC_FP64 = 1 } deam_precision;
 typedef enum {
   DEAM_W_AM = 0,   /* 4 channels (w~1, w~2, w^1, w^2); objective = masked I-divergence terms */
   DEAM_W_GRAD = 1, /* 2 channels u_i = sum_j (r_j - 1) a_ij; objective = masked NLL terms */
-  DEAM_W_VJP = 2   /* 2 channels u_i = -sum_j v_j a_ij for an upstream v_j = dloss/dg_j */
+  DEAM_W_VJP = 2,  /* 2 channels u_i = -sum_j v_j a_ij for an upstream v_j = dloss/dg_j */
+  DEAM_W_STEP_VJP = 3 /* 2 channels lambda_k = dloss/dl_k for an upstream
+                         v = [4][R] (dloss/dw~_1, dloss/dw~_2, dloss/dw^_1, dloss/dw^_2) */
 } deam_wmode;
 
 /* Workspace queries. */
@@ -80,7 +82,8 @@ typedef enum {
   DEAM_OP_POLY_MEAN = 1,
   DEAM_OP_BACKPROJECT = 2,
   DEAM_OP_ITERATE = 3,
-  DEAM_OP_METAL_TRACE = 4
+  DEAM_OP_METAL_TRACE = 4,
+  DEAM_OP_ITERATE_VJP = 5
 } deam_op;
 
 typedef struct {
@@ -184,6 +187,25 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
 int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
                        const double* Z, int32_t n_iter, double* obj_hist, void* ws,
                        size_t ws_bytes, void* stream, float* kernel_ms);
+
+/* Vector-Jacobian product of one DEAM iteration (the differentiable form of
+ * deam_iterate, for losses on the reconstructed image): with
+ * Phi(c) = c - ln(b~(c) / b^(c)) / Z (the update of deam_update, c unchanged
+ * where b~ <= 0 or b^ <= 0),
+ *   out = (dPhi/dc)^T G = G + H^T lambda,
+ * where u~_i = -G_i / (Z_i b~_i) and u^_i = G_i / (Z_i b^_i) are projected,
+ * alpha = H u~ and beta = H u^, and lambda_k(y) = sum_i alpha_i dw~_i/dl_k +
+ * beta_i dw^_i/dl_k is formed per ray from the second moments
+ * sum_E mu_i(E) mu_k(E) q_j(y,E) (chain rule through Eq. 8 and the weights).
+ * The projections of c are recomputed (nothing is kept from the forward pass).
+ *   c64  [2][V] double: the iterate entering the iteration;
+ *   d    [2][R] float;  mask [R] uint8 or NULL;  Z host [2] double > 0;
+ *   G    [2][V] double: dloss/dPhi;   out [2][V] double output (may not
+ *        alias G or c64).
+ * Workspace: deam_workspace_size(DEAM_OP_ITERATE_VJP). */
+int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
+                     const uint8_t* mask, const double* Z, const double* G, double* out,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* deam_last_error(void);

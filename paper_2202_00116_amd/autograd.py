@@ -9,7 +9,15 @@ PolyForward:  c -> g (2, R), the expected counts of Eq. 8.  Its vector-Jacobian
               product for an upstream v = dloss/dg is -H^T sum_j v_j a_ij
               (one poly-mean pass in VJP mode and one backprojection).
 
-Both keep every step on the GPU library; torch only carries the tensors.
+DEAMStep:     c -> Phi(c) = c - ln(b~(c)/b^(c))/Z, one DEAM iteration on the
+              FP64 image (2, V).  Its vector-Jacobian product (deam_iterate_vjp)
+              recomputes the projections of c (only c is kept per iteration)
+              and costs three forward projections and two backprojections;
+              unrolled_deam chains n iterations, so that a loss on the
+              reconstruction (a learned prior, a task loss) can be
+              differentiated through the reconstruction itself.
+
+All keep every step on the GPU library; torch only carries the tensors.
 """
 from __future__ import annotations
 
@@ -55,3 +63,29 @@ class PolyForward(torch.autograd.Function):
         v = grad_g.to(plan.dtype).contiguous()
         u, _, _ = plan.poly_mean(l, None, None, mode=L.W_VJP, v=v)
         return plan.backproject(u), None
+
+
+class DEAMStep(torch.autograd.Function):
+    """c_next = DEAMStep.apply(c, plan, d, mask, Z); c: float64 (2, V)."""
+
+    @staticmethod
+    def forward(ctx, c, plan, d, mask, Z):
+        c_next = c.detach().clone().contiguous()
+        plan.iterate(c_next, d, mask, Z, 1)
+        ctx.plan, ctx.d, ctx.mask, ctx.Z = plan, d, mask, Z
+        ctx.save_for_backward(c.detach())
+        return c_next
+
+    @staticmethod
+    def backward(ctx, grad):
+        (c,) = ctx.saved_tensors
+        G = grad.to(torch.float64).contiguous()
+        return ctx.plan.iterate_vjp(c.contiguous(), ctx.d, ctx.mask, ctx.Z, G), None, None, None, None
+
+
+def unrolled_deam(c0, plan, d, mask, Z, n_iter):
+    """n_iter differentiable DEAM iterations from c0 (float64 (2, V))."""
+    c = c0
+    for _ in range(n_iter):
+        c = DEAMStep.apply(c, plan, d, mask, Z)
+    return c

@@ -172,6 +172,18 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
     case DEAM_OP_BACKPROJECT:
       L.wmax = take(64);
       break;
+    case DEAM_OP_ITERATE_VJP:
+      take_packed(2 * rs);
+      L.l = take(R * 2 * rs);
+      L.w = take(R * 4 * rs);
+      L.b = take(V * 4 * rs);
+      L.u = take(V * 4 * rs);
+      L.ab = take(R * 4 * rs);
+      L.lam = take(R * 2 * rs);
+      L.bl = take(V * 2 * rs);
+      L.partial = take((size_t)p->ray_blocks * 8);
+      L.wmax = take(64);
+      break;
     case DEAM_OP_ITERATE:
     default:
       take_packed(2 * rs);
@@ -381,7 +393,7 @@ int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels) {
 
 int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes) {
   if (!plan || !bytes) return fail(DEAM_ERR_NULL, "NULL argument");
-  if (op < DEAM_OP_FORWARD || op > DEAM_OP_METAL_TRACE)
+  if (op < DEAM_OP_FORWARD || op > DEAM_OP_ITERATE_VJP)
     return fail(DEAM_ERR_VALUE, "unknown op %d", op);
   *bytes = deam::workspace_layout(plan, op).total;
   return ok();
@@ -431,15 +443,19 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
                    size_t ws_bytes, void* stream) {
   if (int rc = check_plan(plan)) return rc;
   if (!l || !w) return fail(DEAM_ERR_NULL, "l or w is NULL");
-  if (mode != DEAM_W_AM && mode != DEAM_W_GRAD && mode != DEAM_W_VJP)
+  if (mode != DEAM_W_AM && mode != DEAM_W_GRAD && mode != DEAM_W_VJP && mode != DEAM_W_STEP_VJP)
     return fail(DEAM_ERR_VALUE, "unknown weight mode %d", mode);
-  if (mode == DEAM_W_VJP && !v) return fail(DEAM_ERR_NULL, "v is NULL in VJP mode");
+  if ((mode == DEAM_W_VJP || mode == DEAM_W_STEP_VJP) && !v)
+    return fail(DEAM_ERR_NULL, "v is NULL in VJP mode");
   if (mode != DEAM_W_VJP && !d) return fail(DEAM_ERR_NULL, "d is NULL");
   deam::WsLayout L;
   if (int rc = check_ws(plan, DEAM_OP_POLY_MEAN, ws, ws_bytes, L)) return rc;
   char* wsb = (char*)ws;
   hipStream_t st = (hipStream_t)stream;
-  const int pm = mode == DEAM_W_AM ? deam::PM_AM : (mode == DEAM_W_GRAD ? deam::PM_GRAD : deam::PM_VJP);
+  const int pm = mode == DEAM_W_AM     ? deam::PM_AM
+                 : mode == DEAM_W_GRAD ? deam::PM_GRAD
+                 : mode == DEAM_W_VJP  ? deam::PM_VJP
+                                       : deam::PM_STEP;
   uint32_t* wmax = (uint32_t*)(wsb + L.wmax);
   double* partial = (double*)(wsb + L.partial);
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
@@ -560,6 +576,50 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
                  const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
                  void* stream) {
   return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
+}
+
+int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
+                     const uint8_t* mask, const double* Z, const double* G, double* out,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c64 || !d || !Z || !G || !out) return fail(DEAM_ERR_NULL, "c64, d, Z, G or out is NULL");
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  if (out == G || out == c64) return fail(DEAM_ERR_VALUE, "out may not alias G or c64");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_ITERATE_VJP, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  const bool dbl = plan->precision == DEAM_PREC_FP64;
+  const size_t rs = real_size(plan);
+  const size_t V = (size_t)plan->gd.V, R = (size_t)plan->gd.R;
+  void* cpy = w + L.cp_y;
+  void* cpx = w + L.cp_x;
+  uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  double* partial = (double*)(w + L.partial);
+  // forward pass of the iteration, recomputed: l = H c, weights, b = H^T w
+  HIP_TRY(deam::launch_update(plan, const_cast<double*>(c64), nullptr, Z[0], Z[1], nullptr, cpy,
+                              cpx, st));
+  HIP_TRY(deam::launch_zero_tail(plan, cpx, dbl, st));
+  HIP_TRY(deam::launch_forward(plan, cpy, cpx, w + L.l, 2, st));
+  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_AM, nullptr, w + L.w, nullptr,
+                            partial, wmax, st));
+  HIP_TRY(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
+  // upstream images for b~ and b^, and their projections alpha = H u~, beta = H u^
+  HIP_TRY(deam::launch_step_u(plan, G, w + L.b, Z[0], Z[1], w + L.u, st));
+  for (int p = 0; p < 2; ++p) {
+    HIP_TRY(deam::launch_pack(plan, w + L.u + (size_t)p * 2 * V * rs, 2, false, dbl, cpy, cpx, st));
+    HIP_TRY(deam::launch_forward(plan, cpy, cpx, w + L.ab + (size_t)p * 2 * R * rs, 2, st));
+  }
+  // lambda per ray, then out = G + H^T lambda
+  HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_STEP, w + L.ab, w + L.lam, nullptr,
+                            partial, nullptr, st));
+  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_absmax(plan, w + L.lam, 2, wmax, st));
+  HIP_TRY(deam::launch_backproject(plan, w + L.lam, 2, false, wmax, w + L.bl, st));
+  HIP_TRY(deam::launch_add_g(plan, G, w + L.bl, out, st));
+  return ok();
 }
 
 int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,

@@ -76,7 +76,7 @@ struct BpTile {
   static_assert(lds_bytes <= 81920, "backprojection tile exceeds 80 KiB");
 };
 
-enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4 };
+enum PolyMode { PM_L = 0, PM_AM = 1, PM_GRAD = 2, PM_VJP = 3, PM_TRACE = 4, PM_STEP = 5 };
 
 constexpr int kFpBlock = 256;
 
@@ -101,6 +101,8 @@ struct WsLayout {
   size_t partial;        // per-block FP64 partial sums
   size_t wmax;           // per-channel max |w| (uint32 float bits)
   size_t scratch;        // small FP64 scratch
+  size_t l, u, ab, lam, bl;   // iteration VJP: line integrals, upstream images, their
+                              // projections, lambda, its backprojection
   size_t total;
 };
 
@@ -144,6 +146,12 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
 // nonneg: every weight is >= 0 (the AM weights), which allows a cheaper rounding
 hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
                               const uint32_t* wmax, void* b, hipStream_t st);
+// iteration VJP: u = (-G_i/(Z_i b~_i), ..., G_i/(Z_i b^_i)) planar [4][V]
+hipError_t launch_step_u(const deam_plan* p, const double* G, const void* b, double z1, double z2,
+                         void* u, hipStream_t st);
+// out = G + bl (double [2][V])
+hipError_t launch_add_g(const deam_plan* p, const double* G, const void* bl, double* out,
+                        hipStream_t st);
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
                          void* c_proj, void* cp_y, void* cp_x, hipStream_t st);
 

@@ -390,6 +390,51 @@ __device__ void energy_sums(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, 
   a[1][1] = S[5] + C[5];  // sum_E mu2 q_H
 }
 
+// energy_sums plus the second moments m[j] = (sum_E mu1^2 q_j, sum_E mu1 mu2 q_j,
+// sum_E mu2^2 q_j) of both spectra
+template <typename T>
+__device__ void energy_sums2(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, T g[2],
+                             T a[2][2], T m[2][3]) {
+  T S[12], C[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) S[i] = C[i] = 0;
+  for (int e0 = 0; e0 < nE; e0 += 8) {
+    T p[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) p[i] = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const EBin<T> B = eb[e0 + e];
+      const T ex = dexp(-fma(B.mu1, l1, B.mu2 * l2));
+      p[0] = fma(B.i0l, ex, p[0]);
+      p[1] = fma(B.i0h, ex, p[1]);
+      p[2] = fma(B.m1l, ex, p[2]);
+      p[3] = fma(B.m2l, ex, p[3]);
+      p[4] = fma(B.m1h, ex, p[4]);
+      p[5] = fma(B.m2h, ex, p[5]);
+      p[6] = fma(B.mu1 * B.m1l, ex, p[6]);
+      p[7] = fma(B.mu1 * B.m2l, ex, p[7]);
+      p[8] = fma(B.mu2 * B.m2l, ex, p[8]);
+      p[9] = fma(B.mu1 * B.m1h, ex, p[9]);
+      p[10] = fma(B.mu1 * B.m2h, ex, p[10]);
+      p[11] = fma(B.mu2 * B.m2h, ex, p[11]);
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) neumaier(S[i], C[i], p[i]);
+  }
+  g[0] = S[0] + C[0];
+  g[1] = S[1] + C[1];
+  a[0][0] = S[2] + C[2];
+  a[1][0] = S[3] + C[3];
+  a[0][1] = S[4] + C[4];
+  a[1][1] = S[5] + C[5];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    m[0][i] = S[6 + i] + C[6 + i];
+    m[1][i] = S[9 + i] + C[9 + i];
+  }
+}
+
 // I-divergence term d ln(d/g) - d + g, written as g((1+rho) ln(1+rho) - rho)
 // with rho = (d - g)/g so that it does not cancel when d is close to g.
 __device__ __forceinline__ double idiv_term(double d, double g) {
@@ -411,13 +456,44 @@ __device__ void poly_epilogue(const EBin<T>* __restrict__ eb, int nE, T l1, T l2
                               const uint8_t* __restrict__ mask, const T* __restrict__ v,
                               T* __restrict__ w, T* __restrict__ gout, double& term, T wabs[4]) {
   T g[2], a[2][2];
-  energy_sums<T>(eb, nE, l1, l2, g, a);
+  [[maybe_unused]] T m[2][3];
+  if constexpr (MODE == PM_STEP)
+    energy_sums2<T>(eb, nE, l1, l2, g, a, m);
+  else
+    energy_sums<T>(eb, nE, l1, l2, g, a);
   const bool metal = mask != nullptr && mask[ray] != 0;
   if (gout) {
     gout[ray] = g[0];
     gout[R + ray] = g[1];
   }
-  if constexpr (MODE == PM_VJP) {
+  if constexpr (MODE == PM_STEP) {
+    // lambda_k = sum_i alpha_i dw~_i/dl_k + beta_i dw^_i/dl_k with
+    //   dw~_i/dl_k = sum_j (d_j/g_j^2) a_kj a_ij [off the trace] - r_j m_ik^j
+    //   dw^_i/dl_k = -sum_j m_ik^j      (m_ik^j = m[j][i + k])
+    const T dj[2] = {(T)d[ray], (T)d[R + ray]};
+    const T al[2] = {v[ray], v[R + ray]}, be[2] = {v[2 * R + ray], v[3 * R + ray]};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      T lam = 0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        T dwt = 0, dwh = 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const T gj = g[j], mm = m[j][i + k];
+          const T r = metal ? (T)1 : (gj > (T)0 ? dj[j] / gj : (T)0);
+          if (!metal && gj > (T)0) dwt += dj[j] / (gj * gj) * a[k][j] * a[i][j];
+          if (metal || gj > (T)0) dwt -= r * mm;
+          dwh -= mm;
+        }
+        lam = fma(al[i], dwt, fma(be[i], dwh, lam));
+      }
+      w[(int64_t)k * R + ray] = lam;
+      wabs[k] = fabs(lam);
+    }
+    term = 0.0;
+    return;
+  } else if constexpr (MODE == PM_VJP) {
     const T vl = v[ray], vh = v[R + ray];
     const T u1 = -(vl * a[0][0] + vh * a[0][1]);
     const T u2 = -(vl * a[1][0] + vh * a[1][1]);
@@ -1214,6 +1290,35 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
 }
 
 // ---------------------------------------------------------------------------
+// Iteration VJP helpers (voxel-wise)
+// ---------------------------------------------------------------------------
+// u = (dloss/db~_1, dloss/db~_2, dloss/db^_1, dloss/db^_2) for the update
+// c_i - ln(b~_i/b^_i)/Z_i: -G_i/(Z_i b~_i) and G_i/(Z_i b^_i) where the update
+// applies (both > 0), else 0.  FP64 arithmetic, stored in the plan precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_u(int64_t V, const double* __restrict__ G,
+                                                const T* __restrict__ b, double iz1, double iz2,
+                                                T* __restrict__ u) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= V) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double bt = (double)b[i * V + x], bh = (double)b[(2 + i) * V + x];
+    const double g = G[i * V + x] * (i == 0 ? iz1 : iz2);
+    const bool act = bt > 0.0 && bh > 0.0;
+    u[i * V + x] = act ? (T)(-g / bt) : (T)0;
+    u[(2 + i) * V + x] = act ? (T)(g / bh) : (T)0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_add_g(int64_t n, const double* __restrict__ G,
+                                               const T* __restrict__ bl, double* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x < n) out[x] = G[x] + (double)bl[x];
+}
+
+// ---------------------------------------------------------------------------
 // Update and packing (32x32 tiles, LDS transpose for the x-major copy)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1395,8 +1500,11 @@ static void poly_dispatch(const deam_plan* p, const void* l, const float* d, con
   else if (mode == PM_GRAD)
     hipLaunchKernelGGL((k_poly<T, PM_GRAD>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d,
                        mask, (const T*)v, (T*)w, (T*)g, partial, wmax);
-  else
+  else if (mode == PM_VJP)
     hipLaunchKernelGGL((k_poly<T, PM_VJP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
+                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+  else
+    hipLaunchKernelGGL((k_poly<T, PM_STEP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
                        (const T*)v, (T*)w, (T*)g, partial, wmax);
 }
 
@@ -1472,6 +1580,30 @@ hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool 
                       : bp_by_channels<double, false>(p, w, n_ch, nonneg, wmax, b, st);
   return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, nonneg, wmax, b, st)
                     : bp_by_channels<float, false>(p, w, n_ch, nonneg, wmax, b, st);
+}
+
+hipError_t launch_step_u(const deam_plan* p, const double* G, const void* b, double z1, double z2,
+                         void* u, hipStream_t st) {
+  const int64_t V = p->gd.V;
+  const dim3 grid((unsigned)((V + 255) / 256));
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_step_u<double>, grid, dim3(256), 0, st, V, G, (const double*)b, 1.0 / z1,
+                       1.0 / z2, (double*)u);
+  else
+    hipLaunchKernelGGL(k_step_u<float>, grid, dim3(256), 0, st, V, G, (const float*)b, 1.0 / z1,
+                       1.0 / z2, (float*)u);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_g(const deam_plan* p, const double* G, const void* bl, double* out,
+                        hipStream_t st) {
+  const int64_t n = 2 * p->gd.V;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_add_g<double>, grid, dim3(256), 0, st, n, G, (const double*)bl, out);
+  else
+    hipLaunchKernelGGL(k_add_g<float>, grid, dim3(256), 0, st, n, G, (const float*)bl, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,

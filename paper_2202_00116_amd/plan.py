@@ -118,7 +118,7 @@ class Plan:
         if mode != L.W_VJP:
             self._check(d, (2, self.R), torch.float32, "d")
         self._check(mask, (self.R,), torch.uint8, "mask")
-        self._check(v, (2, self.R), self.dtype, "v")
+        self._check(v, (4 if mode == L.W_STEP_VJP else 2, self.R), self.dtype, "v")
         nw = 4 if mode == L.W_AM else 2
         w = torch.empty((nw, self.R), dtype=self.dtype, device=self.device)
         g = torch.empty((2, self.R), dtype=self.dtype, device=self.device) if want_g else None
@@ -160,6 +160,21 @@ class Plan:
                                       Zh.ctypes.data_as(C.c_void_p), int(n_iter), _ptr(obj_hist),
                                       ws, n, _stream()))
         return c64
+
+    def iterate_vjp(self, c64, d, mask, Z, G):
+        """Vector-Jacobian product of one DEAM iteration at c64 for the upstream
+        gradient G (both float64 (2, V)): returns (dPhi/dc)^T G."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(G, (2, self.V), torch.float64, "G")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        out = torch.empty((2, self.V), dtype=torch.float64, device=self.device)
+        ws, n = self.workspace(L.OP_ITERATE_VJP)
+        L.check(self.lib.deam_iterate_vjp(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+                                          Zh.ctypes.data_as(C.c_void_p), _ptr(G), _ptr(out),
+                                          ws, n, _stream()))
+        return out
 
     def iterate_timed(self, c64, d, mask, Z, n_iter, obj_hist=None):
         """iterate() plus per-kernel device times (ms summed over the iterations):

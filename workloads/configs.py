@@ -29,7 +29,7 @@ import numpy as np
 
 from . import geometry as G
 from .physics import ENERGY_KEV, basis_mu, spectra, water_in_basis
-from .phantoms import (EllipticCylinder as E, Cylinder, MaterialPhantom,
+from .phantoms import (EllipticCylinder as E, Cylinder, MaterialPhantom, basis_image,
                        metal_fraction, random_blobs, voxel_centres)
 
 
@@ -178,6 +178,55 @@ def surrogate_Z(geom, mu, I0):
     h(x,y) mu_i(E) / Z_i of any ray sum to at most one."""
     keep = I0.sum(axis=0) > 0
     return 2.0 * mu[:, keep].max(axis=1) * geom.box_diagonal()
+
+
+def unrolled_phantom(seed, scale=1.0):
+    """Seeded phantom of the unrolled-reconstruction workload: a water disk of
+    radius 90 mm with two bone disks and one to three metal rods (diameter
+    3-12 mm, titanium or steel) inside it; lengths scaled by `scale`."""
+    rng = np.random.default_rng(seed)
+    objs = [E(0, 0, 90 * scale, 90 * scale, "water", "air")]
+    placed = []
+
+    def spot(r):
+        for _ in range(1000):
+            rr = (70 * scale - r) * math.sqrt(rng.uniform())
+            th = rng.uniform(0, 2 * math.pi)
+            x, y = rr * math.cos(th), rr * math.sin(th)
+            if all(math.hypot(x - a, y - b) > r + q + 2 * scale for a, b, q in placed):
+                placed.append((x, y, r))
+                return x, y
+        raise RuntimeError("no room for the insert")
+
+    for _ in range(2):
+        r = 12 * scale
+        x, y = spot(r)
+        objs.append(E(x, y, r, r, "bone", "water"))
+    for _ in range(int(rng.integers(1, 4))):
+        r = 0.5 * rng.uniform(3, 12) * scale
+        x, y = spot(r)
+        objs.append(E(x, y, r, r, "titanium" if rng.uniform() < 0.5 else "steel", "water"))
+    return MaterialPhantom(objs)
+
+
+def unrolled_inputs(seed, name="fan256", i0=1e5):
+    """One case of the unrolled-reconstruction workload on a fan-beam
+    geometry: Poisson data of unrolled_phantom(seed), the metal mask, the
+    cold start, Z, the truth in the basis and the non-metal voxels."""
+    geom = geometry_for(name)
+    I0 = spectra(i0)
+    mu = basis_mu()
+    scale = geom.nx * geom.dx / 256.0
+    ph = unrolled_phantom(seed, scale)
+    frac = metal_fraction(ph, geom, 4)
+    metal = (frac >= 0.5).astype(np.uint8).reshape(-1)
+    gbar = expected_counts(geom, ph, I0)
+    rng = np.random.default_rng(seed)
+    d = rng.poisson(gbar).astype(np.float32)
+    return dict(name=name, geom=geom, I0=I0, mu=mu, d=d, gbar=gbar, metal=metal,
+                t=0.5 * min(geom.dx, geom.dy), c0=cold_start(geom, I0), Z=surrogate_Z(geom, mu, I0),
+                c_true=basis_image(ph, geom, I0), keep=(frac.reshape(-1) == 0).astype(np.float64),
+                seed=seed)
 
 
 def blob_inputs(name="fan256", seed_c=4, seed_true=40, i0=1e5, n_blobs=20):

@@ -274,3 +274,25 @@ def metal_fraction(phantom: MaterialPhantom, geom, ss: int):
         sub = frac[iz0:iz1, iy0:iy1, ix0:ix1]
         frac[iz0:iz1, iy0:iy1, ix0:ix1] = np.minimum(sub + f, 1.0)
     return frac if is3d else frac[0]
+
+
+def basis_image(phantom: MaterialPhantom, geom, I0, ss: int = 4):
+    """Basis images (2, V) of a 2D phantom: each of ss x ss sub-samples of a
+    pixel takes the basis fractions of the material of the innermost object
+    containing it (the objects are listed outermost first), averaged."""
+    from .physics import material_in_basis
+    coef = {m: material_in_basis(m, I0) for m in phantom.materials}
+    coef.setdefault("air", np.zeros(2))
+    x0, y0 = -geom.nx * geom.dx / 2, -geom.ny * geom.dy / 2
+    offs = (np.arange(ss) + 0.5) / ss
+    xs = x0 + (np.arange(geom.nx)[:, None] + offs[None, :]).ravel() * geom.dx
+    ys = y0 + (np.arange(geom.ny)[:, None] + offs[None, :]).ravel() * geom.dy
+    X = np.stack(np.meshgrid(xs, ys, indexing="xy"), axis=-1)       # (ny*ss, nx*ss, 2)
+    first = phantom.objects[0].parent if phantom.objects else "air"
+    out = np.zeros(X.shape[:2] + (2,))
+    out[...] = coef.get(first, np.zeros(2))
+    for o in phantom.objects:
+        inside = o.contains(X)
+        out[inside] = coef[o.material]
+    out = out.reshape(geom.ny, ss, geom.nx, ss, 2).mean(axis=(1, 3))
+    return np.ascontiguousarray(out.reshape(-1, 2).T)

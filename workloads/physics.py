@@ -76,15 +76,22 @@ def spectra(i0: float, kvps=(90.0, 140.0), e_kev=ENERGY_KEV):
     return np.stack([spectrum(k, i0, e_kev) for k in kvps])
 
 
-def water_in_basis(I0, e_kev=ENERGY_KEV):
-    """Basis fractions (c1, c2) whose attenuation best matches water, in the
-    least-squares sense over the energies where either spectrum is non-zero,
-    weighted by the summed spectra."""
+def material_in_basis(material, I0, e_kev=ENERGY_KEV):
+    """Basis fractions (c1, c2) whose attenuation best matches a material, in
+    the least-squares sense over the energies where either spectrum is
+    non-zero, weighted by the summed spectra (air: zero)."""
+    if material == "air":
+        return np.zeros(2)
     mb = basis_mu(e_kev)
     w = I0.sum(axis=0)
     keep = w > 0
     sw = np.sqrt(w[keep] / w[keep].sum())
     a = (mb[:, keep] * sw).T
-    b = mu("water", e_kev)[keep] * sw
+    b = mu(material, e_kev)[keep] * sw
     sol, *_ = np.linalg.lstsq(a, b, rcond=None)
     return sol
+
+
+def water_in_basis(I0, e_kev=ENERGY_KEV):
+    """material_in_basis for water."""
+    return material_in_basis("water", I0, e_kev)
