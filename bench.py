@@ -90,6 +90,147 @@ def read_traffic(kernel, workload):
     return None
 
 
+def iteration_model(g, S, nE):
+    """Whole-iteration roofline of the op and byte model: VALU lane-ops
+    (forward 8/segment, energy sums 11/bin/ray + 40/ray, backprojection
+    10/segment, update 32 per voxel-component) and algorithmic HBM bytes
+    (41 B per ray, 96 B per voxel)."""
+    ops = 8.0 * S + (11.0 * nE + 40.0) * g.n_rays + 10.0 * S + 64.0 * g.n_voxels
+    byt = 41.0 * g.n_rays + 96.0 * g.n_voxels
+    return ops, byt
+
+
+def measure(workload, K, W, K64, dev, log):
+    """Mixed-precision step time, per-kernel times, the all-FP64 step time and
+    the roofline figures of one workload (inputs resident in HBM)."""
+    import torch
+    from workloads import make_inputs
+    from paper_2202_00116_amd.plan import Plan
+
+    t_in = time.perf_counter()
+    inp = make_inputs(workload)
+    g = inp["geom"]
+    log(f"inputs {workload}: R={g.n_rays} V={g.n_voxels} ({time.perf_counter() - t_in:.1f} s)")
+    d = torch.from_numpy(inp["d"]).to(dev)
+    M = torch.from_numpy(inp["metal"]).to(dev)
+    c0 = torch.from_numpy(inp["c0"]).to(dev)
+    Z = inp["Z"]
+    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
+    mask = plan.metal_trace(M, inp["t"])
+    torch.cuda.synchronize()
+
+    # whole-step throughput
+    c = c0.clone()
+    hist = torch.zeros(max(K, 1), dtype=torch.float64, device=dev)
+    plan.iterate(c, d, mask, Z, W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.iterate(c, d, mask, Z, K, hist)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / K
+    log(f"mixed: {t_step * 1e3:.3f} ms/step")
+
+    # per-kernel device times (HIP events on the launch stream)
+    ck = c0.clone()
+    plan.iterate(ck, d, mask, Z, 1)
+    kms = plan.iterate_timed(ck, d, mask, Z, K)
+    t_fp_poly, t_bp, t_upd = kms["fp_poly"] / K, kms["backproject"] / K, kms["update"] / K
+    # forward projection alone (2 channels), events on torch's current stream
+    cf = c0.to(torch.float32)
+    plan.forward(cf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        plan.forward(cf)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fp2 = e0.elapsed_time(e1) / K
+    grays = g.n_rays / ((t_fp2 + t_bp) * 1e-3) / 1e9
+
+    # all-FP64 variant
+    plan64 = Plan(g, inp["I0"], inp["mu"], "fp64")
+    c64 = c0.clone()
+    plan64.iterate(c64, d, mask, Z, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan64.iterate(c64, d, mask, Z, K64)
+    torch.cuda.synchronize()
+    t_step64 = (time.perf_counter() - t0) / K64
+    log(f"fp64: {t_step64 * 1e3:.3f} ms/step")
+
+    # roofline of the dominant kernel, and of the whole iteration
+    S = segment_count(g)
+    nE = int((inp["I0"].sum(axis=0) > 0).sum())
+    ops = {"fp_poly": 8.0 * S + (11.0 * nE + 40.0) * g.n_rays, "backproject": 10.0 * S}
+    times = {"fp_poly": t_fp_poly, "backproject": t_bp}
+    dom = max(times, key=times.get)
+    achieved = ops[dom] / (times[dom] * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
+                "traffic": read_traffic(dom, workload), "kernel": dom, "ops_per_launch": ops[dom],
+                "segments": S, "avg_launch_ms": times[dom]}
+    it_ops, it_bytes = iteration_model(g, S, nE)
+    t_valu, t_hbm = it_ops / PEAK_LANE_OPS, it_bytes / PEAK_HBM
+    iteration = {"valu_model_ms": t_valu * 1e3, "hbm_model_ms": t_hbm * 1e3,
+                 "binding": "alu" if t_valu >= t_hbm else "hbm",
+                 "frac_of_binding_roofline": max(t_valu, t_hbm) / t_step,
+                 "hbm_frac": it_bytes / t_step / PEAK_HBM}
+    return dict(inp=inp, plan=plan, d=d, mask=mask, c0=c0, t_step=t_step, grays=grays,
+                kernel_ms={"fp_poly": t_fp_poly, "backproject": t_bp, "update": t_upd,
+                           "forward_2ch": t_fp2},
+                fp64={"iterations_per_s": 1.0 / t_step64, "ms_per_step": t_step64 * 1e3,
+                      "steps": K64},
+                speedup=t_step64 / t_step, roofline=roofline, iteration=iteration)
+
+
+def measure_unrolled(dev, log, batch=8, n_iter=10, reps=3):
+    """Differentiable unrolled DEAM: a batch of seeded phantoms on the 256 x 256
+    fan-beam geometry, n_iter iterations forward and the backward pass to an
+    L2 loss on the non-metal voxels (gradient w.r.t. the starting image)."""
+    import torch
+    from workloads import unrolled_inputs
+    from paper_2202_00116_amd.plan import Plan
+    from paper_2202_00116_amd.autograd import unrolled_deam
+
+    t_in = time.perf_counter()
+    cases = [unrolled_inputs(50 + s) for s in range(batch)]
+    log(f"inputs unrolled: {batch} cases ({time.perf_counter() - t_in:.1f} s)")
+    g = cases[0]["geom"]
+    plan = Plan(g, cases[0]["I0"], cases[0]["mu"], "mixed")
+    data = []
+    for cs in cases:
+        d = torch.from_numpy(cs["d"]).to(dev)
+        mask = plan.metal_trace(torch.from_numpy(cs["metal"]).to(dev), cs["t"])
+        data.append((d, mask, torch.from_numpy(cs["c0"]).to(dev),
+                     torch.from_numpy(cs["keep"]).to(dev), torch.from_numpy(cs["c_true"]).to(dev),
+                     cs["Z"]))
+
+    def run():
+        total = 0.0
+        for d, mask, c0, keep, ct, Z in data:
+            x = c0.clone().requires_grad_(True)
+            cn = unrolled_deam(x, plan, d, mask, Z, n_iter)
+            loss = (keep * (cn - ct) ** 2).sum()
+            loss.backward()
+            total += float(loss.detach())
+        return total
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    log(f"unrolled: {t * 1e3:.2f} ms per batch (forward + backward)")
+    return {"workload": f"batch of {batch} seeded phantoms (water disk, two bone disks, 1-3 Ti/steel rods), "
+                        f"fan-beam 256x256 at 1 mm, {g.n_views} views x {g.n_cols} channels, "
+                        f"{n_iter} unrolled DEAM iterations forward + backward to an L2 loss on the "
+                        f"non-metal voxels",
+            "ms_per_batch": t * 1e3, "cases_per_s": batch / t,
+            "iterations_per_s": batch * n_iter / t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +240,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the helical and unrolled-reconstruction measurements")
+    ap.add_argument("--helical-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -109,8 +253,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from workloads import make_inputs
-    from paper_2202_00116_amd.plan import Plan
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -127,77 +269,11 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
         return
     K, W = args.steps, args.warmup
-    t_in = time.perf_counter()
-    inp = make_inputs(args.workload)
-    g = inp["geom"]
-    t_in = time.perf_counter() - t_in
-    print(f"[bench] inputs {args.workload}: R={g.n_rays} V={g.n_voxels} ({t_in:.1f} s)", file=sys.stderr, flush=True)
-
-    d = torch.from_numpy(inp["d"]).to(dev)
-    M = torch.from_numpy(inp["metal"]).to(dev)
-    c0 = torch.from_numpy(inp["c0"]).to(dev)
-    Z = inp["Z"]
-    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
-    mask = plan.metal_trace(M, inp["t"])
-    torch.cuda.synchronize()
-
-    # --- mixed precision: whole-step throughput ------------------------------
-    c = c0.clone()
-    hist = torch.zeros(max(K, 1), dtype=torch.float64, device=dev)
-    plan.iterate(c, d, mask, Z, W)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.iterate(c, d, mask, Z, K, hist)
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / K
-    print(f"[bench] mixed: {t_step * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # --- per-kernel device times (HIP events on the launch stream) -------------
-    ck = c0.clone()
-    plan.iterate(ck, d, mask, Z, 1)
-    kms = plan.iterate_timed(ck, d, mask, Z, K)
-    t_fp_poly = kms["fp_poly"] / K
-    t_bp = kms["backproject"] / K
-    t_upd = kms["update"] / K
-    # forward projection alone (2 channels), events on torch's current stream
-    cf = c0.to(torch.float32)
-    plan.forward(cf)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(K):
-        plan.forward(cf)
-    e1.record()
-    torch.cuda.synchronize()
-    t_fp2 = e0.elapsed_time(e1) / K
-    grays = g.n_rays / ((t_fp2 + t_bp) * 1e-3) / 1e9
-
-    # --- all-FP64 variant --------------------------------------------------
     K64 = args.fp64_steps if args.fp64_steps is not None else max(2, K // 4)
-    plan64 = Plan(g, inp["I0"], inp["mu"], "fp64")
-    c64 = c0.clone()
-    plan64.iterate(c64, d, mask, Z, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan64.iterate(c64, d, mask, Z, K64)
-    torch.cuda.synchronize()
-    t_step64 = (time.perf_counter() - t0) / K64
-    print(f"[bench] fp64: {t_step64 * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # --- roofline of the dominant kernel ----------------------------------------
-    S = segment_count(g)
-    nE = int((inp["I0"].sum(axis=0) > 0).sum())
-    ops = {
-        "fp_poly": 8.0 * S + (11.0 * nE + 40.0) * g.n_rays,
-        "backproject": 10.0 * S,
-    }
-    times = {"fp_poly": t_fp_poly, "backproject": t_bp}
-    dom = max(times, key=times.get)
-    achieved = ops[dom] / (times[dom] * 1e-3)
-    traffic = read_traffic(dom, args.workload)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "kernel": dom, "ops_per_launch": ops[dom], "segments": S,
-                "avg_launch_ms": times[dom]}
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    m = measure(args.workload, K, W, K64, dev, log)
+    g, inp, t_step = m["inp"]["geom"], m["inp"], m["t_step"]
+    plan, d, mask, c0, Z = m["plan"], m["d"], m["mask"], m["c0"], inp["Z"]
 
     out = {
         "metric": "DEAM iterations/s + Grays/s (fwd+back), FP32 vs FP64 GPU at stated error",
@@ -215,14 +291,15 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
                    "precision": "mixed: f32 projection/energy sums/weights, fixed-point backprojection, "
                                 "f64 objective and update",
-                   "rays": g.n_rays, "voxels": g.n_voxels, "energy_bins": nE,
+                   "rays": g.n_rays, "voxels": g.n_voxels,
+                   "energy_bins": int((inp["I0"].sum(axis=0) > 0).sum()),
                    "metal_rays": int(mask.sum().item())},
-        "grays_per_s": grays,
-        "kernel_ms": {"fp_poly": t_fp_poly, "backproject": t_bp, "update": t_upd,
-                      "forward_2ch": t_fp2},
-        "fp64": {"iterations_per_s": 1.0 / t_step64, "ms_per_step": t_step64 * 1e3, "steps": K64},
-        "speedup_mixed_vs_fp64": t_step64 / t_step,
-        "roofline": roofline,
+        "grays_per_s": m["grays"],
+        "kernel_ms": m["kernel_ms"],
+        "fp64": m["fp64"],
+        "speedup_mixed_vs_fp64": m["speedup"],
+        "roofline": m["roofline"],
+        "iteration_roofline": m["iteration"],
         "cpu_baseline": None,
     }
 
@@ -245,6 +322,22 @@ def main():
                                "sample": f"{n_it} full FP64 oracle DEAM iterations of the {args.workload} "
                                          f"workload from the cold start ({t_cpu:.1f} s)"}
         out["error_vs_oracle"] = {"iterations": n_it, "image_rel_l2": err, "objective_rel": herr}
+
+    # --- secondary workloads: the 3D helical case and the unrolled reconstruction
+    if not args.no_secondary and args.workload != "helical":
+        del m, plan, d, mask, c0
+        torch.cuda.empty_cache()
+        h = measure("helical", args.helical_steps, 1, 1, dev, log)
+        out["helical"] = {"workload": f"helical: {WORKLOAD_DESC['helical']}",
+                          "iterations_per_s": 1.0 / h["t_step"], "ms_per_step": h["t_step"] * 1e3,
+                          "steps": args.helical_steps, "grays_per_s": h["grays"],
+                          "kernel_ms": h["kernel_ms"], "fp64": h["fp64"],
+                          "speedup_mixed_vs_fp64": h["speedup"], "roofline": h["roofline"],
+                          "iteration_roofline": h["iteration"]}
+        del h
+        torch.cuda.empty_cache()
+    if not args.no_secondary:
+        out["unrolled"] = measure_unrolled(dev, log)
     print(json.dumps(out))
 
 
