@@ -767,7 +767,8 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           uint32_t oA, oB;
           step_geom(q, dA, dB, oA, oB, tn);
           const uint32_t z = slice_off(ifloor(fma((tn - t.sa) * t.ida, zr[j], sw)));
-          const T2 vA = *(const T2*)(cpb + oA + z), vB = *(const T2*)(cpb + oB + z);
+          const T2 vA = *(const T2*)(cpb + (uint32_t)(oA + z));
+          const T2 vB = *(const T2*)(cpb + (uint32_t)(oB + z));
           e1 -= fma(dA, vA.x, dB * vB.x);
           e2 -= fma(dA, vA.y, dB * vB.y);
           walk_row<T, true, false>(ry, q, 0, nb, 0, nzz, visit);
@@ -797,8 +798,9 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           C[j] = D;
           zo[j] = slice_off(D);
         }
-        vA[j] = *(const T2*)(cpb + oA + zo[j]);
-        vB[j] = *(const T2*)(cpb + oB + zo[j]);
+        // one 32-bit offset from the uniform base (SGPR-based addressing)
+        vA[j] = *(const T2*)(cpb + (uint32_t)(oA + zo[j]));
+        vB[j] = *(const T2*)(cpb + (uint32_t)(oB + zo[j]));
       }
 #pragma unroll
       for (int j = 0; j < RG; ++j) {
