@@ -91,7 +91,7 @@ inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
   const int64_t ng = (n_rows + rg - 1) / rg;
   return nvb * nkb * ng;
 }
-constexpr int kViewBatch = 32;
+constexpr int kViewBatch = 64;
 
 // Workspace pieces (byte offsets, 256-aligned).
 struct WsLayout {
