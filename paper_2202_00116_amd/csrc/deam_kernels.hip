@@ -943,7 +943,7 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
 }
 
 // View set-up of a tile for one batch of kViewBatch views (all threads of
-// the block take part; two barriers).  For every view of the batch: the
+// the block take part; three barriers).  For every view of the batch: the
 // channels [kl, kl + nk) whose rays can meet the tile, from the channel
 // coordinates of the tile's corners, and the detector rows [rl, rl + nr)
 // whose rays can meet its slices, from its z-range and its distance to the
@@ -954,8 +954,9 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
                                            double Y0, double Y1, double Z0, double Z1,
                                            float (*s_kap)[4], int* s_kl, int* s_nk, int* s_rl,
                                            int* s_nr, int* s_off) {
-  if (threadIdx.x < 4 * kViewBatch) {
-    const int j = threadIdx.x >> 2, cn = threadIdx.x & 3;
+  static_assert(kViewBatch % 64 == 0, "the prefix sum runs over whole waves of views");
+  for (int i = threadIdx.x; i < 4 * kViewBatch; i += blockDim.x) {
+    const int j = i >> 2, cn = i & 3;
     const int v = vb0 + j;
     float kap = 0.f;
     if (v < G.n_views) {
@@ -968,11 +969,11 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
     s_kap[j][cn] = kap;
   }
   __syncthreads();
-  // channel and row ranges of each view and their prefix sum (one wave)
-  if (threadIdx.x < 64) {
-    const int j = threadIdx.x, v = vb0 + j;
+  // channel and row ranges of each view
+  for (int j = threadIdx.x; j < kViewBatch; j += blockDim.x) {
+    const int v = vb0 + j;
     int kl = 0, nk = 0, rl = 0, nr = 0;
-    if (j < kViewBatch && v < G.n_views) {
+    if (v < G.n_views) {
       const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
       const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
       kl = max((int)ceilf(kmn - 0.01f), 0);
@@ -995,20 +996,29 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
         nr = 1;
       }
     }
-    int run = nk * ((nr + RG - 1) / RG);
+    s_kl[j] = kl;
+    s_nk[j] = nk;
+    s_rl[j] = rl;
+    s_nr[j] = nr;
+  }
+  __syncthreads();
+  // exclusive prefix sum of the item counts (one wave, 64 views at a time)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int carry = 0;
+    if (lane == 0) s_off[0] = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int u = __shfl_up(run, d);
-      if (j >= d) run += u;
+    for (int c = 0; c < kViewBatch; c += 64) {
+      int run = s_nk[c + lane] * ((s_nr[c + lane] + RG - 1) / RG);
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(run, d);
+        if (lane >= d) run += u;
+      }
+      run += carry;
+      s_off[c + lane + 1] = run;
+      carry = __shfl(run, 63);
     }
-    if (j < kViewBatch) {
-      s_kl[j] = kl;
-      s_nk[j] = nk;
-      s_rl[j] = rl;
-      s_nr[j] = nr;
-      s_off[j + 1] = run;
-    }
-    if (j == 0) s_off[0] = 0;
   }
   __syncthreads();
 }
