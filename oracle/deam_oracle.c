@@ -25,7 +25,11 @@
  *     energy sums of mu_i p_j and mu_i q_j (the DEAM step the paper cites to
  *     O'Sullivan and Benac; derived from Eqs. 5, 8, 9-10);
  *   - the masked I-divergence of Eq. 5 and the Poisson negative
- *     log-likelihood with its gradient b~ - b^.
+ *     log-likelihood with its gradient b~ - b^;
+ *   - the penalised iteration: the roughness penalty of Eq. 6 with the
+ *     potential of Eq. 7 (read as the convex "fair" potential), and the
+ *     c-step as one convex problem per voxel (De Pierro's decoupling),
+ *     solved by bisection.
  * Everything is FP64; ray sums and energy sums use Neumaier compensation.
  */
 #include "deam_oracle.h"
@@ -489,4 +493,140 @@ double orc_nll_grad(const orc_geom* g, int nE, const double* I0, const double* m
   if (grad) orc_backproject(g, 2, u, grad);
   free(l); free(u); free(obj);
   return s;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Penalised DEAM (Section 2.3, Eqs. 6-7)                                   */
+/* ----------------------------------------------------------------------- */
+
+/* Edge-preserving potential of Eq. 7.  As printed, the sign inside the
+ * logarithm makes phi concave and undefined for |t| >= delta; the reading
+ * used here is the convex "fair" potential of Lange,
+ *   phi(t) = delta^2 (|t|/delta - ln(1 + |t|/delta)),
+ * even, ~ t^2/2 for |t| << delta and ~ delta |t| for |t| >> delta. */
+double orc_fair(double t, double delta) {
+  double a = fabs(t) / delta;
+  return delta * delta * (a - log1p(a));
+}
+
+/* Its derivative phi'(t) = t / (1 + |t|/delta). */
+double orc_fair_d1(double t, double delta) { return t / (1.0 + fabs(t) / delta); }
+
+/* Neighbourhood N_x of Eq. 6: the voxels that differ from x by at most one
+ * step along every axis and lie inside the grid (8 in 2D, 26 in 3D away from
+ * the border), with w(x, x~) = 1 / (physical distance between the centres). */
+static int neighbours(const orc_geom* g, long x, long nb[26], double w[26]) {
+  long nx = g->nx, ny = g->ny, nz = g->nz;
+  long ix = x % nx, iy = (x / nx) % ny, iz = x / (nx * ny);
+  int n = 0;
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        if (!ox && !oy && !oz) continue;
+        long jx = ix + ox, jy = iy + oy, jz = iz + oz;
+        if (jx < 0 || jx >= nx || jy < 0 || jy >= ny || jz < 0 || jz >= nz) continue;
+        double ddx = ox * g->dx, ddy = oy * g->dy, ddz = oz * g->dz;
+        nb[n] = (jz * ny + jy) * nx + jx;
+        w[n] = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+        ++n;
+      }
+  return n;
+}
+
+/* R(c) of Eq. 6 for c [2][V]: lambda sum_i sum_x sum_{x~ in N_x} w phi(c_i(x) - c_i(x~))
+ * (every neighbouring pair enters twice, once from each side). */
+double orc_penalty(const orc_geom* g, const double* c, double lambda, double delta) {
+  long V = orc_n_voxels(g);
+  double total = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : total)
+  for (long x = 0; x < V; ++x) {
+    long nb[26];
+    double w[26];
+    int n = neighbours(g, x, nb, w);
+    double s = 0.0;
+    for (int i = 0; i < 2; ++i)
+      for (int k = 0; k < n; ++k) s += w[k] * orc_fair(c[(long)i * V + x] - c[(long)i * V + nb[k]], delta);
+    total += s;
+  }
+  return lambda * total;
+}
+
+/* Penalised component update.  With the data surrogate of the DEAM step
+ * (convexity of exp, weights h mu_i / Z_i) and De Pierro's decoupling of the
+ * penalty (convexity of phi: c(x) - c(x~) is the mean of 2c(x) - c^k(x) -
+ * c^k(x~) and -(2c(x~) - c^k(x) - c^k(x~))), the c-step separates into one
+ * convex problem per voxel and component:
+ *   minimise  b~ c + (b^/Z) exp(-Z (c - c^k)) + lambda sum_{x~} w phi(2c - c^k(x) - c^k(x~)),
+ * whose derivative
+ *   f'(c) = b~ - b^ exp(-Z (c - c^k)) + 2 lambda sum_{x~} w phi'(2c - c^k(x) - c^k(x~))
+ * increases with c.  Its root lies between the data-only minimiser
+ * c^k - ln(b~/b^)/Z and the penalty-only one, which is inside
+ * [min, max] of (c^k(x) + c^k(x~))/2; it is found by bisection.  Voxels with
+ * b~ <= 0 or b^ <= 0 keep c^k, as in the unpenalised update (lambda = 0 gives
+ * the same update up to rounding).  c_prev and c_next are [2][V], distinct. */
+void orc_update_pen(const orc_geom* g, const double* b, const double Z[2], double lambda,
+                    double delta, const double* c_prev, double* c_next) {
+  long V = orc_n_voxels(g);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long x = 0; x < V; ++x) {
+    long nb[26];
+    double w[26];
+    int n = neighbours(g, x, nb, w);
+    for (int i = 0; i < 2; ++i) {
+      const double* ci = c_prev + (long)i * V;
+      double ck = ci[x];
+      double bt = b[(long)i * V + x], bh = b[(long)(2 + i) * V + x];
+      if (!(bt > 0.0 && bh > 0.0)) {
+        c_next[(long)i * V + x] = ck;
+        continue;
+      }
+      double cu = ck - log(bt / bh) / Z[i];
+      double lo = cu, hi = cu;
+      for (int k = 0; k < n; ++k) {
+        double m = 0.5 * (ck + ci[nb[k]]);
+        if (m < lo) lo = m;
+        if (m > hi) hi = m;
+      }
+      /* f'(lo) <= 0 <= f'(hi); halve until the bracket is below 1e-17 absolute
+       * or cannot be split */
+      for (;;) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi) || hi - lo <= 1e-17) break;
+        double f = bt - bh * exp(-Z[i] * (mid - ck));
+        double p = 0.0;
+        for (int k = 0; k < n; ++k) p += w[k] * orc_fair_d1(2.0 * mid - ck - ci[nb[k]], delta);
+        f += 2.0 * lambda * p;
+        if (f > 0.0) hi = mid;
+        else lo = mid;
+      }
+      c_next[(long)i * V + x] = 0.5 * (lo + hi);
+    }
+  }
+}
+
+/* n_iter penalised DEAM iterations from c (in place); obj_hist[k] (or NULL)
+ * = masked I-divergence + R(c^k) at the iterate entering iteration k. */
+int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* mu,
+                    const double* d, const unsigned char* mask, const double Z[2],
+                    double lambda, double delta, int n_iter, double* c, double* obj_hist) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  double* b = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  double* cp = (double*)malloc(sizeof(double) * (size_t)(2 * V));
+  if (!l || !w || !obj || !b || !cp) {
+    free(l); free(w); free(obj); free(b); free(cp);
+    return -1;
+  }
+  for (int k = 0; k < n_iter; ++k) {
+    orc_forward(g, 2, c, l);
+    orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_AM, NULL, w, NULL, obj);
+    if (obj_hist) obj_hist[k] = orc_sum(R, obj) + orc_penalty(g, c, lambda, delta);
+    orc_backproject(g, 4, w, b);
+    memcpy(cp, c, sizeof(double) * (size_t)(2 * V));
+    orc_update_pen(g, b, Z, lambda, delta, cp, c);
+  }
+  free(l); free(w); free(obj); free(b); free(cp);
+  return 0;
 }

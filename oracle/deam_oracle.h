@@ -47,6 +47,14 @@ int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
                 int n_iter, double* c, double* obj_hist);
 double orc_objective(const orc_geom* g, int nE, const double* I0, const double* mu,
                      const double* d, const unsigned char* mask, const double* c, int mode);
+double orc_fair(double t, double delta);
+double orc_fair_d1(double t, double delta);
+double orc_penalty(const orc_geom* g, const double* c, double lambda, double delta);
+void orc_update_pen(const orc_geom* g, const double* b, const double Z[2], double lambda,
+                    double delta, const double* c_prev, double* c_next);
+int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* mu,
+                    const double* d, const unsigned char* mask, const double Z[2],
+                    double lambda, double delta, int n_iter, double* c, double* obj_hist);
 double orc_nll_grad(const orc_geom* g, int nE, const double* I0, const double* mu,
                     const double* d, const unsigned char* mask, const double* c,
                     double* grad);

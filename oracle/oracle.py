@@ -13,6 +13,10 @@ Each function mirrors one step of the DEAM hot path:
     step_vjp     vector-Jacobian product of one iteration (chain rule through
                  the update, the backprojection, the weights and Eq. 8)
     metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
+    fair, penalty, update_pen, iterate_pen
+                 the penalised iteration: potential of Eq. 7 (the convex
+                 "fair" reading), penalty of Eq. 6, and the decoupled
+                 per-voxel c-step solved by bisection
 """
 from __future__ import annotations
 
@@ -111,6 +115,16 @@ def _setup(L):
     L.orc_nll_grad.restype = C.c_double
     L.orc_step_vjp.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, d1, d1, C.c_void_p]
     L.orc_step_vjp.restype = C.c_int
+    L.orc_fair.argtypes = [C.c_double, C.c_double]
+    L.orc_fair.restype = C.c_double
+    L.orc_fair_d1.argtypes = [C.c_double, C.c_double]
+    L.orc_fair_d1.restype = C.c_double
+    L.orc_penalty.argtypes = [G, d1, C.c_double, C.c_double]
+    L.orc_penalty.restype = C.c_double
+    L.orc_update_pen.argtypes = [G, d1, d1, C.c_double, C.c_double, d1, d1]
+    L.orc_iterate_pen.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_double,
+                                  C.c_double, C.c_int, d1, C.c_void_p]
+    L.orc_iterate_pen.restype = C.c_int
     return L
 
 
@@ -260,3 +274,42 @@ def nll_grad(g, I0, mu, d, mask, c):
                            _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m),
                            _f64(c).reshape(-1), grad.ctypes.data_as(C.c_void_p))
     return L, grad.reshape(2, g.n_voxels)
+
+
+def fair(t, delta):
+    """phi(t) of Eq. 7 (fair reading), elementwise."""
+    f = lib().orc_fair
+    return np.vectorize(lambda x: f(float(x), float(delta)), otypes=[float])(t)
+
+
+def fair_d1(t, delta):
+    f = lib().orc_fair_d1
+    return np.vectorize(lambda x: f(float(x), float(delta)), otypes=[float])(t)
+
+
+def penalty(g, c, lam, delta):
+    """R(c) of Eq. 6 for c (2, V)."""
+    return lib().orc_penalty(C.byref(geom_struct(g)), _f64(c).reshape(-1), float(lam), float(delta))
+
+
+def update_pen(g, b, Z, lam, delta, c_prev):
+    """Penalised c-step from c_prev (2, V) with the backprojections b (4, V)."""
+    out = np.zeros(2 * g.n_voxels)
+    lib().orc_update_pen(C.byref(geom_struct(g)), _f64(b).reshape(-1), _f64(Z), float(lam),
+                         float(delta), _f64(c_prev).reshape(-1), out)
+    return out.reshape(2, g.n_voxels)
+
+
+def iterate_pen(g, I0, mu, d, mask, Z, lam, delta, c0, n_iter):
+    """n_iter penalised DEAM iterations from c0; returns (c, history of the
+    masked I-divergence + R(c))."""
+    c = _f64(c0).copy()
+    hist = np.zeros(max(n_iter, 1))
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().orc_iterate_pen(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                               _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
+                               float(lam), float(delta), n_iter, c.reshape(-1),
+                               hist.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle iterate_pen allocation failed")
+    return c, hist[:n_iter]

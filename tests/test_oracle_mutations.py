@@ -11,6 +11,7 @@ import pytest
 import tests.test_oracle_deam as D
 import tests.test_oracle_geometry as Gm
 import tests.test_oracle_unrolled as U
+import tests.test_oracle_penalty as Pn
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "deam_oracle.c")
@@ -48,6 +49,23 @@ MUTATIONS = {
     "step_vjp_hat_sign": ("dwh -= m[j][i][k];", "dwh += m[j][i][k];"),
     "step_vjp_upstream_sign": ("u[(long)i * V + x] = act ? -gi / (Z[i] * bt) : 0.0;",
                                "u[(long)i * V + x] = act ? gi / (Z[i] * bt) : 0.0;"),
+    "fair_printed_sign": ("return delta * delta * (a - log1p(a));",
+                          "return delta * delta * (a + log1p(-a));"),
+    "fair_d1_unscaled": ("return t / (1.0 + fabs(t) / delta);", "return t / (1.0 + fabs(t));"),
+    "pen_weight_squared": ("w[n] = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);",
+                           "w[n] = 1.0 / (ddx * ddx + ddy * ddy + ddz * ddz);"),
+    "pen_no_z_neighbours": ("for (int oz = -1; oz <= 1; ++oz)", "for (int oz = 0; oz <= 0; ++oz)"),
+    "pen_chain_factor": ("f += 2.0 * lambda * p;", "f += lambda * p;"),
+    "pen_neighbour_sign": ("p += w[k] * orc_fair_d1(2.0 * mid - ck - ci[nb[k]], delta);",
+                           "p += w[k] * orc_fair_d1(2.0 * mid - ck + ci[nb[k]], delta);"),
+    "pen_data_term": ("double f = bt - bh * exp(-Z[i] * (mid - ck));",
+                      "double f = bt - bh * exp(Z[i] * (mid - ck));"),
+    "pen_bisection_side": ("if (f > 0.0) hi = mid;", "if (f < 0.0) hi = mid;"),
+    "pen_skipped_voxel": ("        c_next[(long)i * V + x] = ck;\n        continue;",
+                          "        continue;"),
+    "pen_history_without_penalty": (
+        "obj_hist[k] = orc_sum(R, obj) + orc_penalty(g, c, lambda, delta);",
+        "obj_hist[k] = orc_sum(R, obj);"),
 }
 
 PINS = [
@@ -68,6 +86,13 @@ PINS = [
     lambda o: D.test_masked_idiv_nonincreasing(o, "fan64", 20, True),
     lambda o: D.test_gradient_matches_finite_differences(o),
     lambda o: U.test_step_vjp_matches_finite_differences(o),
+    lambda o: Pn.test_fair_potential_closed_forms(o),
+    lambda o: Pn.test_penalty_ramp_2d_closed_form(o, 0.7, 1.3),
+    lambda o: Pn.test_penalty_ramp_3d_closed_form(o),
+    lambda o: Pn.test_update_pen_lambda_zero_is_deam_update(o, Pn.small_box3d),
+    lambda o: Pn.test_update_pen_quadratic_limit_lambert_w(o, Pn.small_box3d),
+    lambda o: Pn.test_update_pen_minimises_voxel_surrogate(o, Pn.small_fan, 5e5, 0.002),
+    lambda o: Pn.test_penalised_objective_decreases(o, 2e5, 0.005),
 ]
 
 
