@@ -104,7 +104,7 @@ def measure(workload, K, W, K64, dev, log):
     """Mixed-precision step time, per-kernel times, the all-FP64 step time and
     the roofline figures of one workload (inputs resident in HBM)."""
     import torch
-    from workloads import make_inputs
+    from workloads import make_inputs, PENALTY
     from paper_2202_00116_amd.plan import Plan
 
     t_in = time.perf_counter()
@@ -158,6 +158,32 @@ def measure(workload, K, W, K64, dev, log):
     t_step64 = (time.perf_counter() - t0) / K64
     log(f"fp64: {t_step64 * 1e3:.3f} ms/step")
 
+    # penalised iteration (Eqs. 6-7) with the workload's (lambda, delta): whole
+    # step, and the penalised update kernel alone on realistic backprojections
+    lam, delta = PENALTY[workload]
+    cpn = c0.clone()
+    plan.iterate_penalized(cpn, d, mask, Z, lam, delta, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.iterate_penalized(cpn, d, mask, Z, lam, delta, K)
+    torch.cuda.synchronize()
+    t_pen = (time.perf_counter() - t0) / K
+    wb, _, _ = plan.poly_mean(plan.forward(cpn.to(plan.dtype)), d, mask)
+    bb = plan.backproject(wb)
+    del wb
+    plan.update_penalized(cpn, bb, Z, lam, delta)
+    e0.record()
+    for _ in range(K):
+        plan.update_penalized(cpn, bb, Z, lam, delta)
+    e1.record()
+    torch.cuda.synchronize()
+    t_upd_pen = e0.elapsed_time(e1) / K
+    del bb
+    log(f"penalized: {t_pen * 1e3:.3f} ms/step, update kernel {t_upd_pen:.3f} ms")
+    penalized = {"lambda": lam, "delta": delta, "ms_per_step": t_pen * 1e3,
+                 "iterations_per_s": 1.0 / t_pen, "steps": K, "update_pen_ms": t_upd_pen,
+                 "update_ms": t_upd}
+
     # roofline of the dominant kernel, and of the whole iteration
     S = segment_count(g)
     nE = int((inp["I0"].sum(axis=0) > 0).sum())
@@ -180,7 +206,8 @@ def measure(workload, K, W, K64, dev, log):
                            "forward_2ch": t_fp2},
                 fp64={"iterations_per_s": 1.0 / t_step64, "ms_per_step": t_step64 * 1e3,
                       "steps": K64},
-                speedup=t_step64 / t_step, roofline=roofline, iteration=iteration)
+                speedup=t_step64 / t_step, roofline=roofline, iteration=iteration,
+                penalized=penalized)
 
 
 def measure_unrolled(dev, log, batch=8, n_iter=10, reps=3):
@@ -300,6 +327,7 @@ def main():
         "speedup_mixed_vs_fp64": m["speedup"],
         "roofline": m["roofline"],
         "iteration_roofline": m["iteration"],
+        "penalized": m["penalized"],
         "cpu_baseline": None,
     }
 
@@ -333,7 +361,7 @@ def main():
                           "steps": args.helical_steps, "grays_per_s": h["grays"],
                           "kernel_ms": h["kernel_ms"], "fp64": h["fp64"],
                           "speedup_mixed_vs_fp64": h["speedup"], "roofline": h["roofline"],
-                          "iteration_roofline": h["iteration"]}
+                          "iteration_roofline": h["iteration"], "penalized": h["penalized"]}
         del h
         torch.cuda.empty_cache()
     if not args.no_secondary:

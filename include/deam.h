@@ -83,7 +83,9 @@ typedef enum {
   DEAM_OP_BACKPROJECT = 2,
   DEAM_OP_ITERATE = 3,
   DEAM_OP_METAL_TRACE = 4,
-  DEAM_OP_ITERATE_VJP = 5
+  DEAM_OP_ITERATE_VJP = 5,
+  DEAM_OP_PENALTY = 6,
+  DEAM_OP_ITERATE_PENALIZED = 7
 } deam_op;
 
 typedef struct {
@@ -206,6 +208,43 @@ int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const
 int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
                      const uint8_t* mask, const double* Z, const double* G, double* out,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* Penalised DEAM (Section 2.3, Eqs. 6-7).  The penalty is
+ *   R(c) = lambda sum_i sum_x sum_{x~ in N_x} w(x,x~) phi(c_i(x) - c_i(x~)),
+ * N_x = the voxels one step away along every axis inside the grid (8 in 2D,
+ * 26 in 3D), w = 1 / (distance between the voxel centres in mm), and phi the
+ * potential of Eq. 7 read as the convex "fair" potential
+ *   phi(t) = delta^2 (|t|/delta - ln(1 + |t|/delta))
+ * (the printed sign inside the logarithm would make it concave and undefined
+ * for |t| >= delta).  lambda >= 0 and delta > 0, both finite; otherwise
+ * DEAM_ERR_VALUE. */
+
+/* R(c) for c64 [2][V] double, into the device scalar out (FP64, deterministic).
+ * Workspace: deam_workspace_size(DEAM_OP_PENALTY). */
+int deam_penalty(const deam_plan* plan, const double* c64, double lambda, double delta,
+                 double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Penalised component update.  The DEAM data surrogate plus De Pierro's
+ * decoupling of R make the c-step one convex problem per voxel and component:
+ *   c_i(x) = argmin_c  b~ c + (b^/Z_i) exp(-Z_i (c - c_prev)) +
+ *            lambda sum_{x~ in N_x} w phi(2c - c_prev_i(x) - c_prev_i(x~)),
+ * solved in FP64 by safeguarded Newton iterations to about 1e-13 relative;
+ * voxels with b~ <= 0 or b^ <= 0 keep c_prev.  lambda = 0 gives deam_update.
+ *   c_prev [2][V] double: the iterate c^k (read only);
+ *   c64    [2][V] double output, must not overlap c_prev;
+ *   b, Z, c_proj as for deam_update. */
+int deam_update_penalized(const deam_plan* plan, const double* c_prev, double* c64, void* c_proj,
+                          const void* b, const double* Z, double lambda, double delta,
+                          void* stream);
+
+/* n_iter penalised DEAM iterations (deam_iterate with the penalised update).
+ * obj_hist (device [n_iter] double or NULL): masked I-divergence + R at the
+ * iterate entering each iteration; it does not increase for FP64 plans.
+ * Workspace: deam_workspace_size(DEAM_OP_ITERATE_PENALIZED). */
+int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
+                           const uint8_t* mask, const double* Z, double lambda, double delta,
+                           int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* deam_last_error(void);

@@ -564,44 +564,56 @@ double orc_penalty(const orc_geom* g, const double* c, double lambda, double del
  * [min, max] of (c^k(x) + c^k(x~))/2; it is found by bisection.  Voxels with
  * b~ <= 0 or b^ <= 0 keep c^k, as in the unpenalised update (lambda = 0 gives
  * the same update up to rounding).  c_prev and c_next are [2][V], distinct. */
+/* The c-step of component i at voxel x (see orc_update_pen). */
+static double pen_voxel(const orc_geom* g, const double* b, const double Z[2], double lambda,
+                        double delta, const double* c_prev, long x, int i) {
+  long V = orc_n_voxels(g);
+  long nb[26];
+  double w[26];
+  int n = neighbours(g, x, nb, w);
+  const double* ci = c_prev + (long)i * V;
+  double ck = ci[x];
+  double bt = b[(long)i * V + x], bh = b[(long)(2 + i) * V + x];
+  if (!(bt > 0.0 && bh > 0.0)) return ck;
+  double cu = ck - log(bt / bh) / Z[i];
+  double lo = cu, hi = cu;
+  for (int k = 0; k < n; ++k) {
+    double m = 0.5 * (ck + ci[nb[k]]);
+    if (m < lo) lo = m;
+    if (m > hi) hi = m;
+  }
+  /* f'(lo) <= 0 <= f'(hi); halve until the bracket is below 1e-17 absolute
+   * or cannot be split */
+  for (;;) {
+    double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi) || hi - lo <= 1e-17) break;
+    double f = bt - bh * exp(-Z[i] * (mid - ck));
+    double p = 0.0;
+    for (int k = 0; k < n; ++k) p += w[k] * orc_fair_d1(2.0 * mid - ck - ci[nb[k]], delta);
+    f += 2.0 * lambda * p;
+    if (f > 0.0) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 void orc_update_pen(const orc_geom* g, const double* b, const double Z[2], double lambda,
                     double delta, const double* c_prev, double* c_next) {
   long V = orc_n_voxels(g);
 #pragma omp parallel for schedule(dynamic, 64)
-  for (long x = 0; x < V; ++x) {
-    long nb[26];
-    double w[26];
-    int n = neighbours(g, x, nb, w);
-    for (int i = 0; i < 2; ++i) {
-      const double* ci = c_prev + (long)i * V;
-      double ck = ci[x];
-      double bt = b[(long)i * V + x], bh = b[(long)(2 + i) * V + x];
-      if (!(bt > 0.0 && bh > 0.0)) {
-        c_next[(long)i * V + x] = ck;
-        continue;
-      }
-      double cu = ck - log(bt / bh) / Z[i];
-      double lo = cu, hi = cu;
-      for (int k = 0; k < n; ++k) {
-        double m = 0.5 * (ck + ci[nb[k]]);
-        if (m < lo) lo = m;
-        if (m > hi) hi = m;
-      }
-      /* f'(lo) <= 0 <= f'(hi); halve until the bracket is below 1e-17 absolute
-       * or cannot be split */
-      for (;;) {
-        double mid = 0.5 * (lo + hi);
-        if (!(mid > lo && mid < hi) || hi - lo <= 1e-17) break;
-        double f = bt - bh * exp(-Z[i] * (mid - ck));
-        double p = 0.0;
-        for (int k = 0; k < n; ++k) p += w[k] * orc_fair_d1(2.0 * mid - ck - ci[nb[k]], delta);
-        f += 2.0 * lambda * p;
-        if (f > 0.0) hi = mid;
-        else lo = mid;
-      }
-      c_next[(long)i * V + x] = 0.5 * (lo + hi);
-    }
-  }
+  for (long x = 0; x < V; ++x)
+    for (int i = 0; i < 2; ++i)
+      c_next[(long)i * V + x] = pen_voxel(g, b, Z, lambda, delta, c_prev, x, i);
+}
+
+/* The penalised c-step at n_sel chosen voxels only: out [2][n_sel]. */
+void orc_update_pen_voxels(const orc_geom* g, const double* b, const double Z[2], double lambda,
+                           double delta, const double* c_prev, long n_sel, const long* voxels,
+                           double* out) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long k = 0; k < n_sel; ++k)
+    for (int i = 0; i < 2; ++i)
+      out[(long)i * n_sel + k] = pen_voxel(g, b, Z, lambda, delta, c_prev, voxels[k], i);
 }
 
 /* n_iter penalised DEAM iterations from c (in place); obj_hist[k] (or NULL)

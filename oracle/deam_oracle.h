@@ -52,6 +52,9 @@ double orc_fair_d1(double t, double delta);
 double orc_penalty(const orc_geom* g, const double* c, double lambda, double delta);
 void orc_update_pen(const orc_geom* g, const double* b, const double Z[2], double lambda,
                     double delta, const double* c_prev, double* c_next);
+void orc_update_pen_voxels(const orc_geom* g, const double* b, const double Z[2], double lambda,
+                           double delta, const double* c_prev, long n_sel, const long* voxels,
+                           double* out);
 int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* mu,
                     const double* d, const unsigned char* mask, const double Z[2],
                     double lambda, double delta, int n_iter, double* c, double* obj_hist);

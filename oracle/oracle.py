@@ -122,6 +122,7 @@ def _setup(L):
     L.orc_penalty.argtypes = [G, d1, C.c_double, C.c_double]
     L.orc_penalty.restype = C.c_double
     L.orc_update_pen.argtypes = [G, d1, d1, C.c_double, C.c_double, d1, d1]
+    L.orc_update_pen_voxels.argtypes = [G, d1, d1, C.c_double, C.c_double, d1, C.c_long, i1, d1]
     L.orc_iterate_pen.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_double,
                                   C.c_double, C.c_int, d1, C.c_void_p]
     L.orc_iterate_pen.restype = C.c_int
@@ -298,6 +299,15 @@ def update_pen(g, b, Z, lam, delta, c_prev):
     lib().orc_update_pen(C.byref(geom_struct(g)), _f64(b).reshape(-1), _f64(Z), float(lam),
                          float(delta), _f64(c_prev).reshape(-1), out)
     return out.reshape(2, g.n_voxels)
+
+
+def update_pen_voxels(g, b, Z, lam, delta, c_prev, voxels):
+    """The penalised c-step at the chosen voxels only: (2, len(voxels))."""
+    vox = np.ascontiguousarray(voxels, dtype=np.int64)
+    out = np.zeros(2 * len(vox))
+    lib().orc_update_pen_voxels(C.byref(geom_struct(g)), _f64(b).reshape(-1), _f64(Z), float(lam),
+                                float(delta), _f64(c_prev).reshape(-1), len(vox), vox, out)
+    return out.reshape(2, len(vox))
 
 
 def iterate_pen(g, I0, mu, d, mask, Z, lam, delta, c0, n_iter):

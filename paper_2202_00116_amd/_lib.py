@@ -15,6 +15,7 @@ FAN2D, HELICAL3D = 0, 1
 PREC_MIXED, PREC_FP64 = 0, 1
 W_AM, W_GRAD, W_VJP, W_STEP_VJP = 0, 1, 2, 3
 OP_FORWARD, OP_POLY_MEAN, OP_BACKPROJECT, OP_ITERATE, OP_METAL_TRACE, OP_ITERATE_VJP = 0, 1, 2, 3, 4, 5
+OP_PENALTY, OP_ITERATE_PENALIZED = 6, 7
 
 STATUS = {0: "DEAM_OK", -1: "DEAM_ERR_NULL", -2: "DEAM_ERR_SHAPE", -3: "DEAM_ERR_GEOMETRY",
           -4: "DEAM_ERR_WORKSPACE", -5: "DEAM_ERR_HIP", -6: "DEAM_ERR_UNSUPPORTED",
@@ -23,6 +24,7 @@ STATUS = {0: "DEAM_OK", -1: "DEAM_ERR_NULL", -2: "DEAM_ERR_SHAPE", -3: "DEAM_ERR
 EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_workspace_size",
            "deam_metal_trace", "deam_forward", "deam_poly_mean", "deam_backproject",
            "deam_update", "deam_iterate", "deam_iterate_timed", "deam_iterate_vjp",
+           "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
            "deam_last_error")
 
 
@@ -68,6 +70,9 @@ def load():
         "deam_iterate": [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
         "deam_iterate_timed": [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp, vp],
         "deam_iterate_vjp": [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp],
+        "deam_penalty": [vp, vp, dp, dp, vp, vp, sz, vp],
+        "deam_update_penalized": [vp, vp, vp, vp, vp, vp, dp, dp, vp],
+        "deam_iterate_penalized": [vp, vp, vp, vp, vp, dp, dp, i32, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -184,6 +184,19 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.partial = take((size_t)p->ray_blocks * 8);
       L.wmax = take(64);
       break;
+    case DEAM_OP_PENALTY:
+      L.partial = take((size_t)pen_blocks(p) * 8);
+      break;
+    case DEAM_OP_ITERATE_PENALIZED:
+      take_packed(2 * rs);
+      L.w = take(R * 4 * rs);
+      L.b = take(V * 4 * rs);
+      L.c_prev = take(V * 2 * 8);
+      // projector partials, then (contiguous) penalty partials: one reduction
+      L.partial = take((nblk + (size_t)pen_blocks(p)) * 8);
+      L.wmax = take(64);
+      L.scratch = take(64);
+      break;
     case DEAM_OP_ITERATE:
     default:
       take_packed(2 * rs);
@@ -393,7 +406,7 @@ int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels) {
 
 int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes) {
   if (!plan || !bytes) return fail(DEAM_ERR_NULL, "NULL argument");
-  if (op < DEAM_OP_FORWARD || op > DEAM_OP_ITERATE_VJP)
+  if (op < DEAM_OP_FORWARD || op > DEAM_OP_ITERATE_PENALIZED)
     return fail(DEAM_ERR_VALUE, "unknown op %d", op);
   *bytes = deam::workspace_layout(plan, op).total;
   return ok();
@@ -491,16 +504,62 @@ int deam_update(const deam_plan* plan, double* c64, void* c_proj, const void* b,
   return ok();
 }
 
+static int check_penalty(double lambda, double delta) {
+  if (!(lambda >= 0.0 && std::isfinite(lambda)))
+    return fail(DEAM_ERR_VALUE, "lambda must be >= 0 and finite");
+  if (!(delta > 0.0 && std::isfinite(delta)))
+    return fail(DEAM_ERR_VALUE, "delta must be > 0 and finite");
+  return DEAM_OK;
+}
+
+int deam_update_penalized(const deam_plan* plan, const double* c_prev, double* c64, void* c_proj,
+                          const void* b, const double* Z, double lambda, double delta,
+                          void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c_prev || !c64 || !b || !Z) return fail(DEAM_ERR_NULL, "c_prev, c64, b or Z is NULL");
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  if (int rc = check_penalty(lambda, delta)) return rc;
+  const size_t nb = (size_t)plan->gd.V * 2 * sizeof(double);
+  const char *a0 = (const char*)c_prev, *b0 = (const char*)c64;
+  if (a0 < b0 + nb && b0 < a0 + nb) return fail(DEAM_ERR_VALUE, "c64 overlaps c_prev");
+  HIP_TRY(deam::launch_update_pen(plan, c_prev, c64, b, Z[0], Z[1], lambda, delta, c_proj,
+                                  nullptr, nullptr, (hipStream_t)stream));
+  return ok();
+}
+
+int deam_penalty(const deam_plan* plan, const double* c64, double lambda, double delta,
+                 double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c64 || !out) return fail(DEAM_ERR_NULL, "c64 or out is NULL");
+  if (int rc = check_penalty(lambda, delta)) return rc;
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_PENALTY, ws, ws_bytes, L)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  double* partial = (double*)((char*)ws + L.partial);
+  HIP_TRY(deam::launch_penalty(plan, c64, lambda, delta, partial, st));
+  HIP_TRY(deam::launch_reduce(partial, deam::pen_blocks(plan), out, st));
+  return ok();
+}
+
+struct PenSpec {
+  double lambda, delta;
+};
+
 static int iterate_impl(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
                         const double* Z, int32_t n_iter, double* obj_hist, void* ws,
-                        size_t ws_bytes, void* stream, float* kernel_ms) {
+                        size_t ws_bytes, void* stream, float* kernel_ms,
+                        const PenSpec* pen = nullptr) {
   if (int rc = check_plan(plan)) return rc;
   if (!c64 || !d || !Z) return fail(DEAM_ERR_NULL, "c64, d or Z is NULL");
   if (n_iter < 0) return fail(DEAM_ERR_VALUE, "n_iter must be >= 0");
   if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
     return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  if (pen)
+    if (int rc = check_penalty(pen->lambda, pen->delta)) return rc;
   deam::WsLayout L;
-  if (int rc = check_ws(plan, DEAM_OP_ITERATE, ws, ws_bytes, L)) return rc;
+  if (int rc = check_ws(plan, pen ? DEAM_OP_ITERATE_PENALIZED : DEAM_OP_ITERATE, ws, ws_bytes, L))
+    return rc;
   char* w = (char*)ws;
   hipStream_t st = (hipStream_t)stream;
   void* cpy = w + L.cp_y;
@@ -541,11 +600,26 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
     STEP(mark(k, 0));
     STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
     STEP(mark(k, 1));
-    if (obj_hist) STEP(deam::launch_reduce(partial, plan->fp_blocks, obj_hist + k, st));
+    if (obj_hist) {
+      int64_t np = plan->fp_blocks;
+      if (pen) {
+        STEP(deam::launch_penalty(plan, c64, pen->lambda, pen->delta, partial + np, st));
+        np += deam::pen_blocks(plan);
+      }
+      STEP(deam::launch_reduce(partial, np, obj_hist + k, st));
+    }
     STEP(mark(k, 2));
     STEP(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
     STEP(mark(k, 3));
-    STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
+    if (pen) {
+      double* cprev = (double*)(w + L.c_prev);
+      STEP(hipMemcpyAsync(cprev, c64, (size_t)plan->gd.V * 2 * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+      STEP(deam::launch_update_pen(plan, cprev, c64, w + L.b, Z[0], Z[1], pen->lambda,
+                                   pen->delta, nullptr, cpy, cpx, st));
+    } else {
+      STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
+    }
     STEP(mark(k, 4));
   }
   if (kernel_ms) {
@@ -576,6 +650,15 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
                  const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
                  void* stream) {
   return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
+}
+
+int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
+                           const uint8_t* mask, const double* Z, double lambda, double delta,
+                           int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
+                           void* stream) {
+  const PenSpec pen{lambda, delta};
+  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr,
+                      &pen);
 }
 
 int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,

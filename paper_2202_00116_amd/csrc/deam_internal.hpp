@@ -103,6 +103,7 @@ struct WsLayout {
   size_t scratch;        // small FP64 scratch
   size_t l, u, ab, lam, bl;   // iteration VJP: line integrals, upstream images, their
                               // projections, lambda, its backprojection
+  size_t c_prev;              // penalised iteration: the iterate entering the update
   size_t total;
 };
 
@@ -154,6 +155,15 @@ hipError_t launch_add_g(const deam_plan* p, const double* G, const void* bl, dou
                         hipStream_t st);
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
                          void* c_proj, void* cp_y, void* cp_x, hipStream_t st);
+// penalised update (Eqs. 6-7): c64 <- argmin of the decoupled per-voxel
+// surrogate around c_prev (distinct from c64), same outputs as launch_update
+hipError_t launch_update_pen(const deam_plan* p, const double* c_prev, double* c64, const void* b,
+                             double z1, double z2, double lambda, double delta, void* c_proj,
+                             void* cp_y, void* cp_x, hipStream_t st);
+// R(c) of Eq. 6: one FP64 partial per block into partial[0, pen_blocks(p))
+hipError_t launch_penalty(const deam_plan* p, const double* c, double lambda, double delta,
+                          double* partial, hipStream_t st);
+int64_t pen_blocks(const deam_plan* p);
 
 WsLayout workspace_layout(const deam_plan* p, int op);
 

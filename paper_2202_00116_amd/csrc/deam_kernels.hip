@@ -1407,6 +1407,216 @@ __global__ __launch_bounds__(256) void k_pack(GeomDev G, const S* __restrict__ c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Penalised update (Eqs. 6-7)
+// ---------------------------------------------------------------------------
+// The roughness penalty lambda sum_i sum_x sum_{x~ in N_x} w(x,x~) phi(c_i(x) -
+// c_i(x~)) with the convex "fair" potential phi(t) = delta^2 (|t|/delta -
+// ln(1 + |t|/delta)), N_x the voxels one step away along every axis (8 in 2D,
+// 26 in 3D) and w = 1 / distance.  De Pierro's decoupling (convexity of phi)
+// and the DEAM data surrogate split the c-step into one convex problem per
+// voxel and component:
+//   minimise b~ c + (b^/Z) exp(-Z (c - c^k)) + lambda sum_n w_n phi(2c - s_n),
+//   s_n = c^k(x) + c^k(x~_n).
+// Its derivative increases with c; the root lies between the data-only
+// minimiser c^k - ln(b~/b^)/Z and [min, max] of s_n / 2 and is found by
+// Newton's method from the data-only minimiser, falling back to bisection
+// whenever a step leaves the bracket.  Everything is FP64.
+struct PenArgs {
+  const double* c_prev;  // [2][V] iterate c^k (all neighbours are read from here)
+  double z1, z2;         // Z_1, Z_2
+  double lam2, lam4;     // 2 lambda, 4 lambda
+  double idelta;         // 1 / delta
+  double delta2;         // delta^2 (penalty value)
+  double w[7];           // 1 / distance by offset class |ox| + 2|oy| + 4|oz| - 1
+};
+
+constexpr int kPenMaxIter = 60;
+
+// 1 / a for a >= 1: hardware reciprocal refined by two Newton-Raphson steps
+// (each squares the relative error), to about one ulp.
+__device__ __forceinline__ double recip_ge1(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return fma(r, fma(-a, r, 1.0), r);
+}
+
+// Root of f'(c) = b~ - b^ exp(-Z (c - c^k)) + 2 lambda sum_n w_n phi'(2c - s_n)
+// inside [lo, hi].  Newton steps from the data-only minimiser; a step that
+// leaves the bracket is replaced by bisection.  A step below
+// 1e-13 (|c| + 1e-3) is taken and ends the iteration (near the root the step
+// falls below one ulp and would otherwise land on a bracket end).
+// Neighbour n has weight P.w[cls_n] when bit n of `in` is set, else 0.
+// ALL: every neighbour is inside the grid (the weights are then uniform).
+template <int NB, bool ALL>
+__device__ __forceinline__ double pen_solve(double ck, double bt, double bh, double Z,
+                                            const double* s, uint32_t in, double lo, double hi,
+                                            const PenArgs& P) {
+  double c = ck - log(bt / bh) / Z;  // data-only minimiser, inside [lo, hi]
+  for (int it = 0; it < kPenMaxIter; ++it) {
+    const double e = bh * exp(-Z * (c - ck));
+    double pf = 0.0, pfp = 0.0;
+    int n = 0;
+#pragma unroll
+    for (int oz = (NB == 26 ? -1 : 0); oz <= (NB == 26 ? 1 : 0); ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (ox == 0 && oy == 0 && oz == 0) continue;
+          const double wc = P.w[(ox != 0) + 2 * (oy != 0) + 4 * (oz != 0) - 1];
+          const double wn = (ALL || ((in >> n) & 1u)) ? wc : 0.0;
+          const double t = 2.0 * c - s[n];
+          const double r = recip_ge1(1.0 + fabs(t) * P.idelta);  // phi'(t) = t r, phi''(t) = r^2
+          pf = fma(wn, t * r, pf);
+          pfp = fma(wn, r * r, pfp);
+          ++n;
+        }
+    const double f = (bt - e) + P.lam2 * pf;
+    const double fp = Z * e + P.lam4 * pfp;
+    if (f > 0.0) hi = c;
+    else if (f < 0.0) lo = c;
+    else break;
+    const double step = f / fp;
+    if (fabs(step) <= 1e-13 * (fabs(c) + 1e-3)) {
+      c -= step;
+      break;
+    }
+    const double cn = c - step;
+    c = (cn > lo && cn < hi) ? cn : 0.5 * (lo + hi);
+  }
+  return c;
+}
+
+// One voxel, both components: gathers the neighbours of c_prev (clamped
+// indices, so every load is in bounds; bit n of `in` marks the neighbours
+// inside the grid) and solves each component.  Voxels with b~ <= 0 or
+// b^ <= 0 keep c^k, as in the unpenalised update.
+template <bool Z3>
+__device__ __forceinline__ void pen_voxel(const GeomDev& G, int ix, int iy, int iz, int64_t idx,
+                                          double bt1, double bt2, double bh1, double bh2,
+                                          const PenArgs& P, double& c1, double& c2) {
+  constexpr int NB = Z3 ? 26 : 8;
+  const int64_t V = G.V;
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    const double* cp = P.c_prev + (i ? V : 0);
+    const double ck = cp[idx];
+    double s[NB];
+    double lo = ck, hi = ck;
+    uint32_t in = 0;
+    int n = 0;
+#pragma unroll
+    for (int oz = (Z3 ? -1 : 0); oz <= (Z3 ? 1 : 0); ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (ox == 0 && oy == 0 && oz == 0) continue;
+          const int jx = min(max(ix + ox, 0), G.nx - 1);
+          const int jy = min(max(iy + oy, 0), G.ny - 1);
+          const int jz = Z3 ? min(max(iz + oz, 0), G.nz - 1) : iz;
+          if (jx == ix + ox && jy == iy + oy && jz == iz + oz) in |= 1u << n;
+          s[n] = ck + cp[((int64_t)jz * G.ny + jy) * G.nx + jx];
+          // the bracket may include clamped (outside) neighbours: it only widens
+          lo = fmin(lo, 0.5 * s[n]);
+          hi = fmax(hi, 0.5 * s[n]);
+          ++n;
+        }
+    const double bt = i ? bt2 : bt1, bh = i ? bh2 : bh1, Z = i ? P.z2 : P.z1;
+    double c = ck;
+    if (bt > 0.0 && bh > 0.0) {
+      const double cu = ck - log(bt / bh) / Z;
+      if (in == (1u << NB) - 1u)
+        c = pen_solve<NB, true>(ck, bt, bh, Z, s, in, fmin(lo, cu), fmax(hi, cu), P);
+      else
+        c = pen_solve<NB, false>(ck, bt, bh, Z, s, in, fmin(lo, cu), fmax(hi, cu), P);
+    }
+    if (i) c2 = c;
+    else c1 = c;
+  }
+}
+
+// One voxel per thread, 32 x 8 tiles; the x-major copy goes through LDS.
+template <typename T, bool Z3>
+__global__ __launch_bounds__(256) void k_update_pen(GeomDev G, PenArgs P, double* __restrict__ c64,
+                                                    const T* __restrict__ b,
+                                                    T* __restrict__ c_proj,
+                                                    typename Vec2<T>::type* __restrict__ cpy,
+                                                    typename Vec2<T>::type* __restrict__ cpx) {
+  using T2 = typename Vec2<T>::type;
+  __shared__ T2 tile[8][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int z = blockIdx.z;
+  const int64_t V = G.V;
+  const int ix = blockIdx.x * 32 + tx, iy = blockIdx.y * 8 + ty;
+  if (ix < G.nx && iy < G.ny) {
+    const int64_t idx = ((int64_t)z * G.ny + iy) * G.nx + ix;
+    double c1, c2;
+    pen_voxel<Z3>(G, ix, iy, z, idx, (double)b[idx], (double)b[V + idx], (double)b[2 * V + idx],
+                  (double)b[3 * V + idx], P, c1, c2);
+    c64[idx] = c1;
+    c64[V + idx] = c2;
+    T2 p;
+    p.x = (T)c1;
+    p.y = (T)c2;
+    if (c_proj) {
+      c_proj[idx] = p.x;
+      c_proj[V + idx] = p.y;
+    }
+    if (cpy) cpy[idx] = p;
+    tile[ty][tx] = p;
+  }
+  if (!cpx) return;
+  __syncthreads();
+  // thread t writes the x-major element (ix = 32 bx + t/8, iy = 8 by + t%8)
+  const int jx = blockIdx.x * 32 + (threadIdx.x >> 3), jy = blockIdx.y * 8 + (threadIdx.x & 7);
+  if (jx < G.nx && jy < G.ny)
+    cpx[((int64_t)z * G.nx + jx) * G.ny + jy] = tile[threadIdx.x & 7][threadIdx.x >> 3];
+}
+
+// R(c): per voxel sum_i sum_n w_n phi(c_i(x) - c_i(x~_n)) (each pair is met
+// from both sides, as in Eq. 6), times lambda; one FP64 partial per block.
+template <bool Z3>
+__global__ __launch_bounds__(256) void k_penalty(GeomDev G, PenArgs P, double lambda,
+                                                 const double* __restrict__ c,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int bx = blockIdx.x, by = blockIdx.y, z = blockIdx.z;
+  const int64_t V = G.V;
+  double acc = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    const int ix = bx * 32 + tx, iy = by * 32 + ty + 8 * j;
+    if (ix >= G.nx || iy >= G.ny) continue;
+    const int64_t idx = ((int64_t)z * G.ny + iy) * G.nx + ix;
+    const double a1 = c[idx], a2 = c[V + idx];
+#pragma unroll
+    for (int oz = (Z3 ? -1 : 0); oz <= (Z3 ? 1 : 0); ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (ox == 0 && oy == 0 && oz == 0) continue;
+          const int jx = ix + ox, jy = iy + oy, jz = z + oz;
+          if (jx < 0 || jx >= G.nx || jy < 0 || jy >= G.ny || jz < 0 || jz >= (Z3 ? G.nz : 1))
+            continue;
+          const int64_t jn = ((int64_t)jz * G.ny + jy) * G.nx + jx;
+          const double u1 = fabs(a1 - c[jn]) * P.idelta, u2 = fabs(a2 - c[V + jn]) * P.idelta;
+          acc += P.w[(ox != 0) + 2 * (oy != 0) + 4 * (oz != 0) - 1] *
+                 ((u1 - log1p(u1)) + (u2 - log1p(u2)));
+        }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    partial[((int64_t)z * gridDim.y + by) * gridDim.x + bx] = lambda * P.delta2 * red[0];
+}
+
 inline dim3 image_grid(const deam_plan* p) {
   return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
 }
@@ -1631,4 +1841,65 @@ hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double 
   return hipGetLastError();
 }
 
+static PenArgs pen_args(const deam_plan* p, const double* c_prev, double z1, double z2,
+                        double lambda, double delta) {
+  PenArgs a{};
+  a.c_prev = c_prev;
+  a.z1 = z1;
+  a.z2 = z2;
+  a.lam2 = 2.0 * lambda;
+  a.lam4 = 4.0 * lambda;
+  a.idelta = 1.0 / delta;
+  a.delta2 = delta * delta;
+  for (int k = 0; k < 7; ++k) {
+    const int m = k + 1;
+    const double ddx = (m & 1) ? p->gd.dx : 0.0, ddy = (m & 2) ? p->gd.dy : 0.0,
+                 ddz = (m & 4) ? p->gd.dz : 0.0;
+    a.w[k] = 1.0 / std::sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+  }
+  return a;
+}
+
+hipError_t launch_update_pen(const deam_plan* p, const double* c_prev, double* c64, const void* b,
+                             double z1, double z2, double lambda, double delta, void* c_proj,
+                             void* cp_y, void* cp_x, hipStream_t st) {
+  const PenArgs a = pen_args(p, c_prev, z1, z2, lambda, delta);
+  const bool z3 = p->gd.is3d && p->gd.nz > 1;
+  const dim3 grid((p->gd.nx + 31) / 32, (p->gd.ny + 7) / 8, p->gd.is3d ? p->gd.nz : 1);
+  if (p->precision == DEAM_PREC_FP64) {
+    if (z3)
+      hipLaunchKernelGGL((k_update_pen<double, true>), grid, dim3(256), 0, st, p->gd, a,
+                         c64, (const double*)b, (double*)c_proj, (double2*)cp_y, (double2*)cp_x);
+    else
+      hipLaunchKernelGGL((k_update_pen<double, false>), grid, dim3(256), 0, st, p->gd, a,
+                         c64, (const double*)b, (double*)c_proj, (double2*)cp_y, (double2*)cp_x);
+  } else {
+    if (z3)
+      hipLaunchKernelGGL((k_update_pen<float, true>), grid, dim3(256), 0, st, p->gd, a,
+                         c64, (const float*)b, (float*)c_proj, (float2*)cp_y, (float2*)cp_x);
+    else
+      hipLaunchKernelGGL((k_update_pen<float, false>), grid, dim3(256), 0, st, p->gd, a,
+                         c64, (const float*)b, (float*)c_proj, (float2*)cp_y, (float2*)cp_x);
+  }
+  return hipGetLastError();
+}
+
+int64_t pen_blocks(const deam_plan* p) {
+  const dim3 g = image_grid(p);
+  return (int64_t)g.x * g.y * g.z;
+}
+
+hipError_t launch_penalty(const deam_plan* p, const double* c, double lambda, double delta,
+                          double* partial, hipStream_t st) {
+  const PenArgs a = pen_args(p, nullptr, 1.0, 1.0, lambda, delta);
+  if (p->gd.is3d && p->gd.nz > 1)
+    hipLaunchKernelGGL(k_penalty<true>, image_grid(p), dim3(256), 0, st, p->gd, a, lambda, c,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_penalty<false>, image_grid(p), dim3(256), 0, st, p->gd, a, lambda, c,
+                       partial);
+  return hipGetLastError();
+}
+
 }  // namespace deam
+

@@ -161,6 +161,44 @@ class Plan:
                                       ws, n, _stream()))
         return c64
 
+    def penalty(self, c64, lam, delta):
+        """R(c) of Eq. 6 (fair potential, 1/distance neighbourhood) as a
+        0-d float64 device tensor."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        ws, n = self.workspace(L.OP_PENALTY)
+        L.check(self.lib.deam_penalty(self._p, _ptr(c64), float(lam), float(delta), _ptr(out),
+                                      ws, n, _stream()))
+        return out
+
+    def update_penalized(self, c_prev, b, Z, lam, delta, want_proj=False):
+        """Penalised c-step from c_prev (float64 (2, V)) with the
+        backprojections b: returns the new iterate (and its projection copy)."""
+        self._check(c_prev, (2, self.V), torch.float64, "c_prev")
+        self._check(b, (4, self.V), self.dtype, "b")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        out = torch.empty((2, self.V), dtype=torch.float64, device=self.device)
+        cp = torch.empty((2, self.V), dtype=self.dtype, device=self.device) if want_proj else None
+        L.check(self.lib.deam_update_penalized(self._p, _ptr(c_prev), _ptr(out), _ptr(cp), _ptr(b),
+                                               Zh.ctypes.data_as(C.c_void_p), float(lam),
+                                               float(delta), _stream()))
+        return (out, cp) if want_proj else out
+
+    def iterate_penalized(self, c64, d, mask, Z, lam, delta, n_iter, obj_hist=None):
+        """n_iter penalised DEAM iterations in place on c64; obj_hist receives
+        the masked I-divergence + R at each iterate."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        ws, n = self.workspace(L.OP_ITERATE_PENALIZED)
+        L.check(self.lib.deam_iterate_penalized(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+                                                Zh.ctypes.data_as(C.c_void_p), float(lam),
+                                                float(delta), int(n_iter), _ptr(obj_hist), ws, n,
+                                                _stream()))
+        return c64
+
     def iterate_vjp(self, c64, d, mask, Z, G):
         """Vector-Jacobian product of one DEAM iteration at c64 for the upstream
         gradient G (both float64 (2, V)): returns (dPhi/dc)^T G."""

@@ -61,8 +61,8 @@ MUTATIONS = {
     "pen_data_term": ("double f = bt - bh * exp(-Z[i] * (mid - ck));",
                       "double f = bt - bh * exp(Z[i] * (mid - ck));"),
     "pen_bisection_side": ("if (f > 0.0) hi = mid;", "if (f < 0.0) hi = mid;"),
-    "pen_skipped_voxel": ("        c_next[(long)i * V + x] = ck;\n        continue;",
-                          "        continue;"),
+    "pen_skipped_voxel": ("if (!(bt > 0.0 && bh > 0.0)) return ck;",
+                          "if (!(bt > 0.0 && bh > 0.0)) return 0.0;"),
     "pen_history_without_penalty": (
         "obj_hist[k] = orc_sum(R, obj) + orc_penalty(g, c, lambda, delta);",
         "obj_hist[k] = orc_sum(R, obj);"),

@@ -60,6 +60,23 @@ WORKLOADS = {
 }
 
 
+# Penalty of the penalised iteration (Eqs. 6-7), (lambda, delta) per workload.
+# The paper gives no values.  delta = 0.005 in basis units (about 0.5% of the
+# water value of the first component).  lambda makes the penalty's curvature
+# in its quadratic regime, 4 lambda sum_{x~} w(x,x~), equal to the median
+# data curvature Z_1 b^_1 over the field of view at the cold start, rounded:
+#   fan64          Z_1 b^_1 ~ 6.0e5, sum w = 6.83 (1 mm)        -> 2.2e4
+#   fan512         Z_1 b^_1 ~ 8.7e4, sum w = 6.97 (0.98 mm)     -> 3.1e3
+#   helical_small  Z_1 b^_1 ~ 2.4e5, sum w = 19.1 (26 nbrs)     -> 3.1e3
+#   helical        Z_1 b^_1 ~ 8.5e4, sum w = 19.4 (26 nbrs)     -> 1.1e3
+PENALTY = {
+    "fan64": (2.2e4, 0.005),
+    "fan512": (3.1e3, 0.005),
+    "helical_small": (3.1e3, 0.005),
+    "helical": (1.1e3, 0.005),
+}
+
+
 def phantom_for(name: str) -> MaterialPhantom:
     if name in ("fan128", "fan64"):
         s = 1.0 if name == "fan128" else 0.5
