@@ -28,7 +28,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 
 from . import geometry as G
-from .physics import ENERGY_KEV, basis_mu, spectra, water_in_basis
+from .physics import ENERGY_KEV, basis_mu, spectra, water_in_basis, mu as material_mu
 from .phantoms import (EllipticCylinder as E, Cylinder, MaterialPhantom, basis_image,
                        metal_fraction, random_blobs, voxel_centres)
 
@@ -75,6 +75,21 @@ PENALTY = {
     "helical_small": (3.1e3, 0.005),
     "helical": (1.1e3, 0.005),
 }
+
+
+def mar_params(geom, I0, e_kev=ENERGY_KEV):
+    """Parameters of the MAR initialisation (Section 2.2).  water_j is the
+    spectrum-weighted attenuation of water (1/mm); the classes of the prior
+    image are relative to it: air below 0.5, soft tissue below 1.5, bone
+    above; metal at 5 or more in the high-energy image (cortical bone is ~3.9x
+    water; a titanium rod of 3 mm radius reconstructs at 5.9-8.6x after beam
+    hardening and partial-volume blur).  eps (line-integral units, ~0.3 mm of water)
+    keeps the NMAR normalisation finite outside the object.  t is the
+    metal-trace threshold of the workloads."""
+    w = material_mu("water", e_kev)
+    water = (I0 @ w) / I0.sum(axis=1)
+    return dict(t=0.5 * min(geom.dx, geom.dy), water=water, air_frac=0.5, bone_frac=1.5,
+                metal_frac=5.0, eps=0.01)
 
 
 def phantom_for(name: str) -> MaterialPhantom:
