@@ -85,7 +85,9 @@ typedef enum {
   DEAM_OP_METAL_TRACE = 4,
   DEAM_OP_ITERATE_VJP = 5,
   DEAM_OP_PENALTY = 6,
-  DEAM_OP_ITERATE_PENALIZED = 7
+  DEAM_OP_ITERATE_PENALIZED = 7,
+  DEAM_OP_FBP = 8,
+  DEAM_OP_MAR_INIT = 9
 } deam_op;
 
 typedef struct {
@@ -245,6 +247,55 @@ int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
                            const uint8_t* mask, const double* Z, double lambda, double delta,
                            int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* MAR initialisation (Section 2.2, Fig. 1, Eq. 4): the initial image of
+ * MAR-DEAM from an analytic reconstruction with normalised metal artifact
+ * reduction (NMAR) of the measured sinograms.  Defined for 2D fan-beam plans
+ * over one full rotation (n_views * 2 pi / views_per_rot = 2 pi) with at most
+ * 4096 channels; other plans return DEAM_ERR_UNSUPPORTED.  Real arrays are in
+ * the plan precision. */
+
+/* Equiangular fan-beam filtered backprojection of n_ch (1 or 2) sinograms of
+ * line integrals p [n_ch][R] into img [n_ch][V]: each view is weighted by
+ * sid cos(gamma), convolved with the sampled ramp kernel g(0) = 1/(8 a^2),
+ * g(j a) = -1/(2 pi^2 sin^2(j a)) for odd j, 0 for even j (a = dgamma), times a,
+ * and backprojected as (2 pi / n_views) sum_v Q_v(gamma') / L^2 with gamma', L
+ * the fan angle and distance of the pixel centre from the source and linear
+ * interpolation between channels (zero outside the detector).  Sums in FP64.
+ * Workspace: deam_workspace_size(DEAM_OP_FBP). */
+int deam_fbp(const deam_plan* plan, const void* p, int32_t n_ch, void* img, void* ws,
+             size_t ws_bytes, void* stream);
+
+/* NMAR across the metal trace, per view and for both sinograms: on a trace
+ * ray the value p / (p_prior + eps) is interpolated linearly along the
+ * channels between the nearest rays off the trace (the nearest one beyond a
+ * detector end) and multiplied by p_prior + eps; other rays are copied.
+ *   p, p_prior, out [2][R] real (out must not overlap p);  mask [R] uint8;
+ *   eps > 0 (line-integral units). */
+int deam_nmar(const deam_plan* plan, const void* p, const uint8_t* mask, const void* p_prior,
+              double eps, void* out, void* stream);
+
+typedef struct {
+  double t;           /* metal-trace threshold, mm of metal path (as deam_metal_trace) */
+  double water[2];    /* spectrum-weighted attenuation of water, low / high (1/mm), > 0 */
+  double air_frac;    /* prior: mu < air_frac * water_j -> 0 */
+  double bone_frac;   /* prior: mu < bone_frac * water_j -> water_j, else mu kept */
+  double metal_frac;  /* metal image: mu_H >= metal_frac * water_H */
+  double eps;         /* NMAR normalisation offset, > 0 */
+} deam_mar_params;
+
+/* The whole initialisation from the counts d [2][R] float:
+ *   p_j = ln(sum_E I0_j) - ln(max(d_j, 1)); mu0 = FBP(p);
+ *   M = [mu0_H >= metal_frac water_H] (output [V] uint8);
+ *   mask = [H M >= t] (output [R] uint8, the trace used by DEAM);
+ *   prior_j = 0 below air_frac water_j, water_j below bone_frac water_j or on
+ *   M, mu0_j above;  p~ = NMAR(p, mask, H prior, eps);  mu1 = FBP(p~);
+ *   c64 = Mt^-1 (mu1_L, mu1_H) (Eq. 4, output [2][V] double), with
+ *   Mt[j][i] = sum_E I0_j(E) mu_i(E) / sum_E I0_j(E) from the plan's tables.
+ * Thresholds are compared in the plan precision.
+ * Workspace: deam_workspace_size(DEAM_OP_MAR_INIT). */
+int deam_mar_init(const deam_plan* plan, const float* d, const deam_mar_params* prm, double* c64,
+                  uint8_t* M, uint8_t* mask, void* ws, size_t ws_bytes, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* deam_last_error(void);

@@ -15,7 +15,7 @@ FAN2D, HELICAL3D = 0, 1
 PREC_MIXED, PREC_FP64 = 0, 1
 W_AM, W_GRAD, W_VJP, W_STEP_VJP = 0, 1, 2, 3
 OP_FORWARD, OP_POLY_MEAN, OP_BACKPROJECT, OP_ITERATE, OP_METAL_TRACE, OP_ITERATE_VJP = 0, 1, 2, 3, 4, 5
-OP_PENALTY, OP_ITERATE_PENALIZED = 6, 7
+OP_PENALTY, OP_ITERATE_PENALIZED, OP_FBP, OP_MAR_INIT = 6, 7, 8, 9
 
 STATUS = {0: "DEAM_OK", -1: "DEAM_ERR_NULL", -2: "DEAM_ERR_SHAPE", -3: "DEAM_ERR_GEOMETRY",
           -4: "DEAM_ERR_WORKSPACE", -5: "DEAM_ERR_HIP", -6: "DEAM_ERR_UNSUPPORTED",
@@ -25,7 +25,7 @@ EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_wor
            "deam_metal_trace", "deam_forward", "deam_poly_mean", "deam_backproject",
            "deam_update", "deam_iterate", "deam_iterate_timed", "deam_iterate_vjp",
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
-           "deam_last_error")
+           "deam_fbp", "deam_nmar", "deam_mar_init", "deam_last_error")
 
 
 class DeamGeometry(C.Structure):
@@ -35,6 +35,11 @@ class DeamGeometry(C.Structure):
                 ("sid", C.c_double), ("sdd", C.c_double), ("dgamma", C.c_double),
                 ("col_offset", C.c_double), ("drow_iso", C.c_double), ("beta0", C.c_double),
                 ("views_per_rot", C.c_double), ("feed_per_rot", C.c_double)]
+
+
+class DeamMarParams(C.Structure):
+    _fields_ = [("t", C.c_double), ("water", C.c_double * 2), ("air_frac", C.c_double),
+                ("bone_frac", C.c_double), ("metal_frac", C.c_double), ("eps", C.c_double)]
 
 
 class DeamError(RuntimeError):
@@ -73,6 +78,9 @@ def load():
         "deam_penalty": [vp, vp, dp, dp, vp, vp, sz, vp],
         "deam_update_penalized": [vp, vp, vp, vp, vp, vp, dp, dp, vp],
         "deam_iterate_penalized": [vp, vp, vp, vp, vp, dp, dp, i32, vp, vp, sz, vp],
+        "deam_fbp": [vp, vp, i32, vp, vp, sz, vp],
+        "deam_nmar": [vp, vp, vp, vp, dp, vp, vp],
+        "deam_mar_init": [vp, vp, C.POINTER(DeamMarParams), vp, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

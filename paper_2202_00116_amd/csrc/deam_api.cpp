@@ -197,6 +197,19 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.wmax = take(64);
       L.scratch = take(64);
       break;
+    case DEAM_OP_FBP:
+      L.q = take(R * 2 * rs);
+      break;
+    case DEAM_OP_MAR_INIT:
+      take_packed(2 * 8);  // FP64 copies of M for the trace; then the prior's copies
+      L.p = take(R * 2 * rs);
+      L.q = take(R * 2 * rs);
+      L.mu0 = take(V * 2 * rs);
+      L.prior = take(V * 2 * rs);
+      L.pp = take(R * 2 * rs);
+      L.pc = take(R * 2 * rs);
+      L.mu1 = take(V * 2 * rs);
+      break;
     case DEAM_OP_ITERATE:
     default:
       take_packed(2 * rs);
@@ -258,7 +271,11 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   const double x0 = -0.5 * g.nx * g.dx, y0 = -0.5 * g.ny * g.dy;
   const int nzv = is3d ? g.nz : 1;
   const double z0 = -0.5 * nzv * g.dz;
-  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_rows * 4);
+  // 2D fan-beam full scans also get the FBP tables of the MAR initialisation
+  const bool fbp_ok = !is3d && g.n_rows == 1 && g.n_cols <= deam::kMaxFbpCols &&
+                      std::fabs(g.n_views * 2.0 * M_PI / g.views_per_rot - 2.0 * M_PI) <= 1e-9;
+  std::vector<double> tab((size_t)g.n_views * 4 + (size_t)g.n_rows * 4 +
+                          (fbp_ok ? (size_t)2 * g.n_cols : 0));
   double* tv = tab.data();
   double* tr = tv + (size_t)g.n_views * 4;
   for (int v = 0; v < g.n_views; ++v) {
@@ -276,6 +293,17 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     tr[4 * r + 1] = std::sqrt(g.sdd * g.sdd + zeta * zeta);
     tr[4 * r + 2] = zeta != 0.0 ? g.dz / zeta : 0.0;
     tr[4 * r + 3] = 0.0;
+  }
+  if (fbp_ok) {
+    // equiangular ramp kernel g(j), j = 0..n-1, and pre-weights sid cos(gamma_k)
+    double* tg = tr + (size_t)g.n_rows * 4;
+    for (int j = 0; j < g.n_cols; ++j) {
+      const double sj = std::sin(j * g.dgamma);
+      tg[j] = j == 0 ? 1.0 / (8.0 * g.dgamma * g.dgamma)
+                     : (j % 2 ? -1.0 / (2.0 * M_PI * M_PI * sj * sj) : 0.0);
+    }
+    for (int k = 0; k < g.n_cols; ++k)
+      tg[g.n_cols + k] = g.sid * std::cos(((double)k - 0.5 * (g.n_cols - 1) - g.col_offset) * g.dgamma);
   }
   // in-plane ray of every (view, channel), walked along its driving axis
   const size_t nvk = (size_t)g.n_views * g.n_cols;
@@ -374,6 +402,29 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
   G.V = (int64_t)g.nx * g.ny * G.nz;
 
+  p->d_fbp = fbp_ok ? G.row + (size_t)g.n_rows * 4 : nullptr;
+  // photons per ray and spectrum-weighted attenuation (Eq. 4's weights)
+  for (int j = 0; j < 2; ++j) {
+    double t = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int e = 0; e < n_energy; ++e) {
+      const double i0 = I0[(size_t)j * n_energy + e];
+      t += i0;
+      m1 += i0 * mu[e];
+      m2 += i0 * mu[(size_t)n_energy + e];
+    }
+    p->i0sum[j] = t;
+    p->mu_eff[j][0] = t > 0.0 ? m1 / t : 0.0;
+    p->mu_eff[j][1] = t > 0.0 ? m2 / t : 0.0;
+  }
+  {
+    const double a = p->mu_eff[0][0], b = p->mu_eff[0][1], c = p->mu_eff[1][0], d = p->mu_eff[1][1];
+    const double det = a * d - b * c;
+    const double id = det != 0.0 ? 1.0 / det : 0.0;
+    p->mu_eff_inv[0][0] = d * id;
+    p->mu_eff_inv[0][1] = -b * id;
+    p->mu_eff_inv[1][0] = -c * id;
+    p->mu_eff_inv[1][1] = a * id;
+  }
   p->h1_bound = h1_bound(g);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
   p->ray_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
@@ -406,7 +457,7 @@ int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels) {
 
 int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes) {
   if (!plan || !bytes) return fail(DEAM_ERR_NULL, "NULL argument");
-  if (op < DEAM_OP_FORWARD || op > DEAM_OP_ITERATE_PENALIZED)
+  if (op < DEAM_OP_FORWARD || op > DEAM_OP_MAR_INIT)
     return fail(DEAM_ERR_VALUE, "unknown op %d", op);
   *bytes = deam::workspace_layout(plan, op).total;
   return ok();
@@ -659,6 +710,77 @@ int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
   const PenSpec pen{lambda, delta};
   return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr,
                       &pen);
+}
+
+static int check_fbp(const deam_plan* plan) {
+  if (!plan->d_fbp)
+    return fail(DEAM_ERR_UNSUPPORTED,
+                "the MAR initialisation needs a 2D fan-beam plan over one full rotation with at "
+                "most %d channels",
+                deam::kMaxFbpCols);
+  return DEAM_OK;
+}
+
+int deam_fbp(const deam_plan* plan, const void* p, int32_t n_ch, void* img, void* ws,
+             size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!p || !img) return fail(DEAM_ERR_NULL, "p or img is NULL");
+  if (n_ch != 1 && n_ch != 2) return fail(DEAM_ERR_SHAPE, "n_ch must be 1 or 2 (got %d)", n_ch);
+  if (int rc = check_fbp(plan)) return rc;
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_FBP, ws, ws_bytes, L)) return rc;
+  HIP_TRY(deam::launch_fbp(plan, p, n_ch, (char*)ws + L.q, img, (hipStream_t)stream));
+  return ok();
+}
+
+int deam_nmar(const deam_plan* plan, const void* p, const uint8_t* mask, const void* p_prior,
+              double eps, void* out, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!p || !mask || !p_prior || !out) return fail(DEAM_ERR_NULL, "p, mask, p_prior or out is NULL");
+  if (int rc = check_fbp(plan)) return rc;
+  if (!(eps > 0.0 && std::isfinite(eps))) return fail(DEAM_ERR_VALUE, "eps must be > 0 and finite");
+  const size_t nb = (size_t)plan->gd.R * 2 * real_size(plan);
+  const char *a0 = (const char*)p, *b0 = (const char*)out;
+  if (a0 < b0 + nb && b0 < a0 + nb) return fail(DEAM_ERR_VALUE, "out overlaps p");
+  HIP_TRY(deam::launch_nmar(plan, p, mask, p_prior, eps, out, (hipStream_t)stream));
+  return ok();
+}
+
+int deam_mar_init(const deam_plan* plan, const float* d, const deam_mar_params* prm, double* c64,
+                  uint8_t* M, uint8_t* mask, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!d || !prm || !c64 || !M || !mask) return fail(DEAM_ERR_NULL, "d, prm, c64, M or mask is NULL");
+  if (int rc = check_fbp(plan)) return rc;
+  const double vals[] = {prm->t, prm->water[0], prm->water[1], prm->air_frac, prm->bone_frac,
+                         prm->metal_frac, prm->eps};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(DEAM_ERR_VALUE, "MAR parameters must be finite");
+  if (!(prm->water[0] > 0.0 && prm->water[1] > 0.0 && prm->eps > 0.0))
+    return fail(DEAM_ERR_VALUE, "water attenuations and eps must be > 0");
+  if (!(plan->i0sum[0] > 0.0 && plan->i0sum[1] > 0.0))
+    return fail(DEAM_ERR_VALUE, "both spectra must have photons");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_MAR_INIT, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  const bool dbl = plan->precision == DEAM_PREC_FP64;
+  // line integrals and their FBP
+  HIP_TRY(deam::launch_line_integrals(plan, d, w + L.p, st));
+  HIP_TRY(deam::launch_fbp(plan, w + L.p, 2, w + L.q, w + L.mu0, st));
+  // metal image, its trace, the prior images and their projections
+  HIP_TRY(deam::launch_mar_classes(plan, w + L.mu0, prm->water, prm->air_frac, prm->bone_frac,
+                                   prm->metal_frac, M, w + L.prior, st));
+  HIP_TRY(deam::launch_pack(plan, M, 1, true, true, w + L.cp_y, w + L.cp_x, st));
+  HIP_TRY(deam::launch_metal_trace(plan, w + L.cp_y, w + L.cp_x, prm->t, mask, nullptr, st));
+  HIP_TRY(deam::launch_pack(plan, w + L.prior, 2, false, dbl, w + L.cp_y,
+                            w + L.cp_y + (size_t)plan->gd.V * 2 * real_size(plan), st));
+  HIP_TRY(deam::launch_forward(plan, w + L.cp_y, w + L.cp_y + (size_t)plan->gd.V * 2 * real_size(plan),
+                               w + L.pp, 2, st));
+  // NMAR, FBP of the corrected sinograms, Eq. 4
+  HIP_TRY(deam::launch_nmar(plan, w + L.p, mask, w + L.pp, prm->eps, w + L.pc, st));
+  HIP_TRY(deam::launch_fbp(plan, w + L.pc, 2, w + L.q, w + L.mu1, st));
+  HIP_TRY(deam::launch_decompose(plan, w + L.mu1, c64, st));
+  return ok();
 }
 
 int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,

@@ -92,6 +92,7 @@ inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
   return nvb * nkb * ng;
 }
 constexpr int kViewBatch = 64;
+constexpr int kMaxFbpCols = 4096;   // FBP filter: one detector row of p and g in LDS (64 KiB)
 
 // Workspace pieces (byte offsets, 256-aligned).
 struct WsLayout {
@@ -104,6 +105,9 @@ struct WsLayout {
   size_t l, u, ab, lam, bl;   // iteration VJP: line integrals, upstream images, their
                               // projections, lambda, its backprojection
   size_t c_prev;              // penalised iteration: the iterate entering the update
+  size_t p, q, mu0, prior, pp, pc, mu1;   // MAR initialisation: line integrals, filtered
+                                          // copy, FBP images, prior, its projection,
+                                          // corrected line integrals, corrected FBP
   size_t total;
 };
 
@@ -123,6 +127,14 @@ struct deam_plan {
   double hmax;                   // upper bound of one h(x,y): the voxel diagonal
   int64_t fp_blocks;             // blocks of the fused projector kernel (its FP64 partials)
   int64_t ray_blocks;            // blocks of one-thread-per-ray kernels
+  // MAR initialisation (2D fan-beam full scans): ramp kernel g(0..n-1) and
+  // pre-weights sid cos(gamma_k) in d_tables (NULL when not supported),
+  // photons per ray of each spectrum, and the inverse of the spectrum-weighted
+  // attenuation matrix Mt[j][i] = sum_E I0_j mu_i / sum_E I0_j
+  const double* d_fbp;
+  double i0sum[2];
+  double mu_eff[2][2];
+  double mu_eff_inv[2][2];
 };
 
 namespace deam {
@@ -164,6 +176,17 @@ hipError_t launch_update_pen(const deam_plan* p, const double* c_prev, double* c
 hipError_t launch_penalty(const deam_plan* p, const double* c, double lambda, double delta,
                           double* partial, hipStream_t st);
 int64_t pen_blocks(const deam_plan* p);
+// MAR initialisation: line integrals [2][R]; FBP of n_ch sinograms through
+// the filtered copy q [n_ch][R]; NMAR; metal and prior images; Eq. 4
+hipError_t launch_line_integrals(const deam_plan* p, const float* d, void* out, hipStream_t st);
+hipError_t launch_fbp(const deam_plan* p, const void* sino, int n_ch, void* q, void* img,
+                      hipStream_t st);
+hipError_t launch_nmar(const deam_plan* p, const void* sino, const uint8_t* mask, const void* pp,
+                       double eps, void* out, hipStream_t st);
+hipError_t launch_mar_classes(const deam_plan* p, const void* mu0, const double water[2],
+                              double fa, double fb, double fm, uint8_t* M, void* prior,
+                              hipStream_t st);
+hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hipStream_t st);
 
 WsLayout workspace_layout(const deam_plan* p, int op);
 

@@ -1617,6 +1617,166 @@ __global__ __launch_bounds__(256) void k_penalty(GeomDev G, PenArgs P, double la
     partial[((int64_t)z * gridDim.y + by) * gridDim.x + bx] = lambda * P.delta2 * red[0];
 }
 
+// ---------------------------------------------------------------------------
+// MAR initialisation (Section 2.2, Fig. 1, Eq. 4), 2D fan-beam full scans
+// ---------------------------------------------------------------------------
+// p_j = ln(sum_E I0_j) - ln(max(d_j, 1)): counts below one photon count as one.
+template <typename T>
+__global__ __launch_bounds__(256) void k_line_integrals(int64_t R, const float* __restrict__ d,
+                                                        double lt1, double lt2, T* __restrict__ p) {
+  const int64_t y = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (y >= R) return;
+  p[y] = (T)(lt1 - log(fmax((double)d[y], 1.0)));
+  p[R + y] = (T)(lt2 - log(fmax((double)d[R + y], 1.0)));
+}
+
+// Ramp filtering of one view of one sinogram per block (equiangular fan beam):
+//   Q_v[k] = a sum_m p_v[m] w[m] g(|k - m|),  w[m] = sid cos(gamma_m),
+//   g(0) = 1/(8 a^2), g(j odd) = -1/(2 pi^2 sin^2(j a)), g(j even) = 0,
+// a = dgamma.  tab = [g(0..n-1), w(0..n-1)] (FP64, from the plan).  The
+// weighted row and the kernel sit in LDS; sums are FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fbp_filter(int n_cols, int64_t R, const T* __restrict__ p,
+                                                    const double* __restrict__ tab, double a,
+                                                    T* __restrict__ Q) {
+  extern __shared__ double sh_fbp[];
+  double* rw = sh_fbp;
+  double* gk = sh_fbp + n_cols;
+  const int v = blockIdx.x, c = blockIdx.y;
+  const int64_t base = (int64_t)c * R + (int64_t)v * n_cols;
+  for (int k = threadIdx.x; k < n_cols; k += 256) {
+    rw[k] = (double)p[base + k] * tab[n_cols + k];
+    gk[k] = tab[k];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_cols; k += 256) {
+    double acc = rw[k] * gk[0];
+    for (int j = 1; j < n_cols; j += 2) {
+      const int lo = k - j, hi = k + j;
+      const double s = (lo >= 0 ? rw[lo] : 0.0) + (hi < n_cols ? rw[hi] : 0.0);
+      acc = fma(s, gk[j], acc);
+    }
+    Q[base + k] = (T)(a * acc);
+  }
+}
+
+// Distance-weighted backprojection of n_ch filtered sinograms, one thread per
+// pixel: f(x) = (2 pi / n_views) sum_v Q_v(gamma') / L^2, where gamma' and L are
+// the fan angle and the distance of the pixel centre seen from the source of
+// view v, and Q_v is interpolated linearly between channels (zero outside the
+// detector).  Geometry in the plan precision, sums in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fbp_bp(GeomDev G, int n_ch, const T* __restrict__ Q,
+                                                double scale, T* __restrict__ img) {
+  const int64_t V = (int64_t)G.nx * G.ny;
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= V) return;
+  const int ix = (int)(x % G.nx), iy = (int)(x / G.nx);
+  const T px = (T)(G.x0 + (ix + 0.5) * G.dx), py = (T)(G.y0 + (iy + 0.5) * G.dy);
+  const T sid = (T)G.sid, ida = (T)(1.0 / G.dgamma), kc = (T)G.kc;
+  const int n = G.n_cols;
+  const int64_t R = G.R;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int v = 0; v < G.n_views; ++v) {
+    const T cb = (T)G.view[4 * v], sb = (T)G.view[4 * v + 1];
+    const T vx = px - sid * cb, vy = py - sid * sb;
+    // central ray u = -(cos b, sin b): cross(u, v) and dot(u, v)
+    const T gam = atan2(sb * vx - cb * vy, -(cb * vx + sb * vy));
+    const T L2 = vx * vx + vy * vy;
+    const T kf = gam * ida + kc;
+    const T fk = floor(kf);
+    const int k0 = (int)fk;
+    if (k0 < -1 || k0 > n - 1) continue;
+    const T fr = kf - fk;
+    const int64_t r0 = (int64_t)v * n + k0;
+    const T q00 = k0 >= 0 ? Q[r0] : (T)0, q01 = k0 + 1 < n ? Q[r0 + 1] : (T)0;
+    acc0 += (double)(((T)1 - fr) * q00 + fr * q01) / (double)L2;
+    if (n_ch > 1) {
+      const T q10 = k0 >= 0 ? Q[R + r0] : (T)0, q11 = k0 + 1 < n ? Q[R + r0 + 1] : (T)0;
+      acc1 += (double)(((T)1 - fr) * q10 + fr * q11) / (double)L2;
+    }
+  }
+  img[x] = (T)(scale * acc0);
+  if (n_ch > 1) img[V + x] = (T)(scale * acc1);
+}
+
+// NMAR (normalised interpolation across the trace), one view per block: on a
+// trace channel k the value p/(pp + eps) is interpolated linearly between the
+// nearest non-trace channels on either side (the nearest one beyond a detector
+// end) and multiplied back by pp + eps; other channels are copied.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nmar(int n_cols, int64_t R, const T* __restrict__ p,
+                                              const uint8_t* __restrict__ mask,
+                                              const T* __restrict__ pp, double eps,
+                                              T* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * n_cols;
+  for (int k = threadIdx.x; k < n_cols; k += 256) {
+    const int64_t y = row + k;
+    if (!mask[y]) {
+      out[y] = p[y];
+      out[R + y] = p[R + y];
+      continue;
+    }
+    int kl = k - 1, kr = k + 1;
+    while (kl >= 0 && mask[row + kl]) --kl;
+    while (kr < n_cols && mask[row + kr]) ++kr;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int64_t o = (int64_t)c * R;
+      if (kl < 0 && kr >= n_cols) {
+        out[o + y] = p[o + y];
+        continue;
+      }
+      double val;
+      if (kl < 0) {
+        val = (double)p[o + row + kr] / ((double)pp[o + row + kr] + eps);
+      } else if (kr >= n_cols) {
+        val = (double)p[o + row + kl] / ((double)pp[o + row + kl] + eps);
+      } else {
+        const double fl = (double)p[o + row + kl] / ((double)pp[o + row + kl] + eps);
+        const double fh = (double)p[o + row + kr] / ((double)pp[o + row + kr] + eps);
+        val = (fh - fl) / (double)(kr - kl) * (double)(k - kl) + fl;
+      }
+      out[o + y] = (T)(val * ((double)pp[o + y] + eps));
+    }
+  }
+}
+
+// Metal image and prior images from the uncorrected FBP images mu0 (L, H):
+// M = [mu_H >= thr_m]; prior_j = 0 below thr_air_j, water_j below thr_bone_j
+// or on M, mu_j above.  Thresholds are compared in the plan precision.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mar_classes(int64_t V, const T* __restrict__ mu0,
+                                                     double wl, double wh, double fa, double fb,
+                                                     double fm, uint8_t* __restrict__ M,
+                                                     T* __restrict__ prior) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= V) return;
+  const T ml = mu0[x], mh = mu0[V + x];
+  const bool metal = mh >= (T)(fm * wh);
+  M[x] = metal ? 1 : 0;
+  const T w[2] = {(T)wl, (T)wh};
+  const T m[2] = {ml, mh};
+  const double wd[2] = {wl, wh};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    T q = m[j] < (T)(fa * wd[j]) ? (T)0 : (m[j] < (T)(fb * wd[j]) ? w[j] : m[j]);
+    prior[j * V + x] = metal ? w[j] : q;
+  }
+}
+
+// Eq. 4: c = Mt^-1 (mu_L, mu_H) per voxel (inverse from the plan, FP64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_decompose(int64_t V, const T* __restrict__ mu,
+                                                   double a00, double a01, double a10, double a11,
+                                                   double* __restrict__ c) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= V) return;
+  const double ml = (double)mu[x], mh = (double)mu[V + x];
+  c[x] = a00 * ml + a01 * mh;
+  c[V + x] = a10 * ml + a11 * mh;
+}
+
 inline dim3 image_grid(const deam_plan* p) {
   return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
 }
@@ -1901,5 +2061,83 @@ hipError_t launch_penalty(const deam_plan* p, const double* c, double lambda, do
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// MAR initialisation launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_line_integrals(const deam_plan* p, const float* d, void* out, hipStream_t st) {
+  const int64_t R = p->gd.R;
+  const dim3 grid((unsigned)((R + 255) / 256));
+  const double lt1 = std::log(p->i0sum[0]), lt2 = std::log(p->i0sum[1]);
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_line_integrals<double>, grid, dim3(256), 0, st, R, d, lt1, lt2,
+                       (double*)out);
+  else
+    hipLaunchKernelGGL(k_line_integrals<float>, grid, dim3(256), 0, st, R, d, lt1, lt2,
+                       (float*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fbp(const deam_plan* p, const void* sino, int n_ch, void* q, void* img,
+                      hipStream_t st) {
+  const int n = p->gd.n_cols;
+  const dim3 fgrid((unsigned)p->gd.n_views, (unsigned)n_ch);
+  const size_t lds = (size_t)2 * n * sizeof(double);
+  const int64_t V = (int64_t)p->gd.nx * p->gd.ny;
+  const dim3 bgrid((unsigned)((V + 255) / 256));
+  const double scale = 2.0 * M_PI / p->gd.n_views;
+  if (p->precision == DEAM_PREC_FP64) {
+    hipLaunchKernelGGL(k_fbp_filter<double>, fgrid, dim3(256), lds, st, n, p->gd.R,
+                       (const double*)sino, p->d_fbp, p->gd.dgamma, (double*)q);
+    hipLaunchKernelGGL(k_fbp_bp<double>, bgrid, dim3(256), 0, st, p->gd, n_ch, (const double*)q,
+                       scale, (double*)img);
+  } else {
+    hipLaunchKernelGGL(k_fbp_filter<float>, fgrid, dim3(256), lds, st, n, p->gd.R,
+                       (const float*)sino, p->d_fbp, p->gd.dgamma, (float*)q);
+    hipLaunchKernelGGL(k_fbp_bp<float>, bgrid, dim3(256), 0, st, p->gd, n_ch, (const float*)q,
+                       scale, (float*)img);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_nmar(const deam_plan* p, const void* sino, const uint8_t* mask, const void* pp,
+                       double eps, void* out, hipStream_t st) {
+  const dim3 grid((unsigned)p->gd.n_views);
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_nmar<double>, grid, dim3(256), 0, st, p->gd.n_cols, p->gd.R,
+                       (const double*)sino, mask, (const double*)pp, eps, (double*)out);
+  else
+    hipLaunchKernelGGL(k_nmar<float>, grid, dim3(256), 0, st, p->gd.n_cols, p->gd.R,
+                       (const float*)sino, mask, (const float*)pp, eps, (float*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mar_classes(const deam_plan* p, const void* mu0, const double water[2],
+                              double fa, double fb, double fm, uint8_t* M, void* prior,
+                              hipStream_t st) {
+  const int64_t V = p->gd.V;
+  const dim3 grid((unsigned)((V + 255) / 256));
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_mar_classes<double>, grid, dim3(256), 0, st, V, (const double*)mu0,
+                       water[0], water[1], fa, fb, fm, M, (double*)prior);
+  else
+    hipLaunchKernelGGL(k_mar_classes<float>, grid, dim3(256), 0, st, V, (const float*)mu0,
+                       water[0], water[1], fa, fb, fm, M, (float*)prior);
+  return hipGetLastError();
+}
+
+hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hipStream_t st) {
+  const int64_t V = p->gd.V;
+  const dim3 grid((unsigned)((V + 255) / 256));
+  const double* a = &p->mu_eff_inv[0][0];
+  if (p->precision == DEAM_PREC_FP64)
+    hipLaunchKernelGGL(k_decompose<double>, grid, dim3(256), 0, st, V, (const double*)mu, a[0],
+                       a[1], a[2], a[3], c64);
+  else
+    hipLaunchKernelGGL(k_decompose<float>, grid, dim3(256), 0, st, V, (const float*)mu, a[0], a[1],
+                       a[2], a[3], c64);
+  return hipGetLastError();
+}
+
 }  // namespace deam
+
 

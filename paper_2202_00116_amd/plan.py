@@ -199,6 +199,42 @@ class Plan:
                                                 _stream()))
         return c64
 
+    def fbp(self, p):
+        """Fan-beam FBP of line integrals p (n_ch, R), n_ch in {1, 2}: (n_ch, V)."""
+        n_ch = p.shape[0]
+        self._check(p, (n_ch, self.R), self.dtype, "p")
+        img = torch.empty((n_ch, self.V), dtype=self.dtype, device=self.device)
+        ws, n = self.workspace(L.OP_FBP)
+        L.check(self.lib.deam_fbp(self._p, _ptr(p), n_ch, _ptr(img), ws, n, _stream()))
+        return img
+
+    def nmar(self, p, mask, p_prior, eps):
+        """NMAR of both sinograms p (2, R) across the trace mask with the prior's
+        projections p_prior (2, R)."""
+        self._check(p, (2, self.R), self.dtype, "p")
+        self._check(p_prior, (2, self.R), self.dtype, "p_prior")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        out = torch.empty_like(p)
+        L.check(self.lib.deam_nmar(self._p, _ptr(p), _ptr(mask), _ptr(p_prior), float(eps),
+                                   _ptr(out), _stream()))
+        return out
+
+    def mar_init(self, d, prm):
+        """MAR initialisation from the counts d (2, R) float32 with the
+        parameters prm (dict: t, water (2,), air_frac, bone_frac, metal_frac,
+        eps): returns (c64 (2, V) float64, M (V,) uint8, mask (R,) uint8)."""
+        self._check(d, (2, self.R), torch.float32, "d")
+        P = L.DeamMarParams(float(prm["t"]), (C.c_double * 2)(*[float(x) for x in prm["water"]]),
+                            float(prm["air_frac"]), float(prm["bone_frac"]),
+                            float(prm["metal_frac"]), float(prm["eps"]))
+        c = torch.empty((2, self.V), dtype=torch.float64, device=self.device)
+        M = torch.empty(self.V, dtype=torch.uint8, device=self.device)
+        mask = torch.empty(self.R, dtype=torch.uint8, device=self.device)
+        ws, n = self.workspace(L.OP_MAR_INIT)
+        L.check(self.lib.deam_mar_init(self._p, _ptr(d), C.byref(P), _ptr(c), _ptr(M), _ptr(mask),
+                                       ws, n, _stream()))
+        return c, M, mask
+
     def iterate_vjp(self, c64, d, mask, Z, G):
         """Vector-Jacobian product of one DEAM iteration at c64 for the upstream
         gradient G (both float64 (2, V)): returns (dPhi/dc)^T G."""

@@ -1,0 +1,147 @@
+"""MAR initialisation on the GPU (Section 2.2, Fig. 1, Eq. 4) against the
+oracle: the fan-beam FBP on narrow, wide and offset geometries, NMAR on
+trace runs including the detector ends, and the whole initialisation on the
+128 x 128 and 512 x 512 fan-beam workloads (metal image and trace compared
+exactly where the threshold decision is not within rounding of the
+threshold)."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import make_inputs, mar_params
+import workloads.geometry as Gw
+from tests.test_oracle_mar import offset_fan, wide_fan, _trace_mask
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+# FP32 plans place a pixel on the detector with an FP32 channel coordinate
+# (|k| <= 2 n_cols): its rounding, ~2^-24 * 2 n_cols (1e-4 channel at 816
+# channels), times the largest channel-to-channel step of the filtered test
+# sinogram (<= its maximum) bounds the error relative to the image maximum.
+TOL = {"mixed": 1e-4, "fp64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def mo():
+    from oracle import mar_oracle
+    return mar_oracle
+
+
+def _plan(g, I0, mu, prec):
+    from paper_2202_00116_amd.plan import Plan
+    return Plan(g, I0, mu, prec)
+
+
+def _spectra():
+    from workloads.physics import basis_mu, spectra
+    return spectra(1e5), basis_mu()
+
+
+def _relmax(a, b):
+    return float(np.abs(np.asarray(a, float) - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("geo", ["fan128", "offset", "wide", "fan512"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_fbp_matches_oracle(mo, geo, prec):
+    from workloads.configs import geometry_for
+    g = {"offset": offset_fan, "wide": wide_fan}.get(geo, lambda: geometry_for(geo))()
+    I0, mu = _spectra()
+    plan = _plan(g, I0, mu, prec)
+    rng = np.random.default_rng(95)
+    # smooth sinogram of an object plus noise, both channels
+    k = np.arange(g.n_cols)
+    prof = np.maximum(0.0, 1.0 - ((k - g.n_cols / 2) / (0.4 * g.n_cols)) ** 2) * 6.0
+    p = np.stack([np.tile(prof, g.n_views), np.tile(0.8 * prof, g.n_views)])
+    p = p + 0.05 * rng.standard_normal(p.shape)
+    pt = torch.tensor(p, dtype=plan.dtype, device=DEV)
+    ref = mo.fbp(g, pt.cpu().numpy().astype(np.float64))
+    out = plan.fbp(pt).cpu().numpy()
+    e = _relmax(out, ref)
+    print(f"{geo} {prec}: FBP max rel err {e:.3e}")
+    assert e <= TOL[prec]
+    one = plan.fbp(pt[:1].contiguous()).cpu().numpy()
+    assert np.array_equal(one[0], out[0])
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_nmar_matches_oracle(mo, prec):
+    g = Gw.fan2d(16, 1.0, 6, 40)
+    I0, mu = _spectra()
+    plan = _plan(g, I0, mu, prec)
+    rng = np.random.default_rng(96)
+    runs = [(0, 10, 17), (1, 0, 5), (2, 33, 40), (3, 12, 13), (4, 3, 9), (4, 20, 31)]
+    mask = _trace_mask(g, runs)
+    p = rng.uniform(0.0, 8.0, (2, g.n_rays))
+    pp = rng.uniform(0.0, 8.0, (2, g.n_rays))
+    pt = torch.tensor(p, dtype=plan.dtype, device=DEV)
+    ppt = torch.tensor(pp, dtype=plan.dtype, device=DEV)
+    ref = mo.nmar(g, pt.cpu().numpy().astype(float), mask, ppt.cpu().numpy().astype(float), 0.01)
+    out = plan.nmar(pt, torch.tensor(mask, device=DEV), ppt, 0.01).cpu().numpy()
+    assert _relmax(out, ref) <= (1e-6 if prec == "mixed" else 1e-15)
+    off = mask == 0
+    assert np.array_equal(out[:, off], pt.cpu().numpy()[:, off])
+    # a fully masked view is copied
+    full = np.zeros_like(mask)
+    full[:g.n_cols] = 1
+    out = plan.nmar(pt, torch.tensor(full, device=DEV), ppt, 0.01)
+    assert torch.equal(out, pt)
+
+
+@pytest.mark.parametrize("name", ["fan128", "fan512"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mar_init_matches_oracle(mo, name, prec):
+    inp = make_inputs(name)
+    g = inp["geom"]
+    prm = mar_params(g, inp["I0"])
+    ref = mo.mar_init(g, inp["I0"], inp["mu"], inp["d"], prm)
+    plan = _plan(g, inp["I0"], inp["mu"], prec)
+    c, M, mask = plan.mar_init(torch.tensor(inp["d"], device=DEV), prm)
+    c, M, mask = c.cpu().numpy(), M.cpu().numpy(), mask.cpu().numpy()
+    # threshold decisions: equal wherever the FBP value is not within the
+    # precision's rounding of the threshold
+    thr = prm["metal_frac"] * prm["water"][1]
+    margin = np.abs(ref["mu0"][1] - thr) / thr
+    sure = margin > (1e-4 if prec == "mixed" else 1e-10)
+    print(f"{name} {prec}: min metal-threshold margin {margin.min():.2e}, "
+          f"{int((~sure).sum())} undecided voxels")
+    assert np.array_equal(M[sure], ref["M"][sure])
+    if np.array_equal(M, ref["M"]):
+        assert np.array_equal(mask, ref["mask"])
+    e = float(np.linalg.norm(c - ref["c"]) / np.linalg.norm(ref["c"]))
+    print(f"{name} {prec}: c rel err {e:.3e}, metal voxels {int(M.sum())}, trace rays {int(mask.sum())}")
+    assert e <= (5e-4 if prec == "mixed" else 1e-10)
+
+
+def test_mar_init_rejects_helical_plan():
+    from paper_2202_00116_amd._lib import DeamError
+    inp = make_inputs("helical_small", with_data=False)
+    plan = _plan(inp["geom"], inp["I0"], inp["mu"], "mixed")
+    with pytest.raises(DeamError, match="UNSUPPORTED"):
+        plan.fbp(torch.zeros((1, plan.R), dtype=torch.float32, device=DEV))
+    with pytest.raises(DeamError, match="UNSUPPORTED"):
+        plan.mar_init(torch.zeros((2, plan.R), dtype=torch.float32, device=DEV),
+                      mar_params(inp["geom"], inp["I0"]))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_deam_from_mar_initialisation(mo, prec, tol):
+    """The 128 x 128 workload as its configuration states it: the MAR
+    initialisation supplies c^0 and the metal trace, then 20 DEAM iterations;
+    against the oracle doing the same from its own initialisation."""
+    from oracle import oracle as O
+    inp = make_inputs("fan128")
+    g = inp["geom"]
+    prm = mar_params(g, inp["I0"])
+    ref0 = mo.mar_init(g, inp["I0"], inp["mu"], inp["d"], prm)
+    ref, href = O.iterate(g, inp["I0"], inp["mu"], inp["d"], ref0["mask"], inp["Z"], ref0["c"], 20)
+    plan = _plan(g, inp["I0"], inp["mu"], prec)
+    d = torch.tensor(inp["d"], device=DEV)
+    c, M, mask = plan.mar_init(d, prm)
+    h = torch.zeros(20, dtype=torch.float64, device=DEV)
+    plan.iterate(c, d, mask, inp["Z"], 20, h)
+    e = float(np.linalg.norm(c.cpu().numpy() - ref) / np.linalg.norm(ref))
+    eh = float(np.abs(h.cpu().numpy() - href).max() / abs(href[0]))
+    print(f"fan128 {prec}: DEAM from the MAR image, 20 it.: image rel {e:.3e}, objective rel {eh:.3e}")
+    assert e <= tol and eh <= tol
+    assert np.all(np.diff(href) < 0)
