@@ -642,3 +642,42 @@ int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* m
   free(l); free(w); free(obj); free(b); free(cp);
   return 0;
 }
+
+/* ----------------------------------------------------------------------- */
+/* Ordered subsets of views                                                  */
+/* ----------------------------------------------------------------------- */
+
+/* n_iter epochs of ordered-subset DEAM: the views are split into n_sub
+ * interleaved subsets (view v belongs to subset v mod n_sub), and each epoch
+ * runs one DEAM step per subset s = 0, 1, ..., n_sub - 1 in which only the rays
+ * of subset s are backprojected (their weights are kept, all others are set
+ * to zero).  obj_hist[k] (or NULL) = masked I-divergence at the iterate
+ * entering epoch k.  n_sub = 1 is the DEAM iteration. */
+int orc_iterate_os(const orc_geom* g, int nE, const double* I0, const double* mu,
+                   const double* d, const unsigned char* mask, const double Z[2], int n_sub,
+                   int n_iter, double* c, double* obj_hist) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  long per_view = (long)g->n_rows * g->n_cols;
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  double* b = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  if (!l || !w || !obj || !b || n_sub < 1) {
+    free(l); free(w); free(obj); free(b);
+    return -1;
+  }
+  for (int k = 0; k < n_iter; ++k) {
+    for (int s = 0; s < n_sub; ++s) {
+      orc_forward(g, 2, c, l);
+      orc_poly_mean(R, nE, I0, mu, l, d, mask, ORC_W_AM, NULL, w, NULL, obj);
+      if (s == 0 && obj_hist) obj_hist[k] = orc_sum(R, obj);
+      for (long y = 0; y < R; ++y)
+        if ((y / per_view) % n_sub != s)
+          for (int ch = 0; ch < 4; ++ch) w[(long)ch * R + y] = 0.0;
+      orc_backproject(g, 4, w, b);
+      orc_update(V, b, Z, c);
+    }
+  }
+  free(l); free(w); free(obj); free(b);
+  return 0;
+}

@@ -58,6 +58,9 @@ void orc_update_pen_voxels(const orc_geom* g, const double* b, const double Z[2]
 int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* mu,
                     const double* d, const unsigned char* mask, const double Z[2],
                     double lambda, double delta, int n_iter, double* c, double* obj_hist);
+int orc_iterate_os(const orc_geom* g, int nE, const double* I0, const double* mu,
+                   const double* d, const unsigned char* mask, const double Z[2], int n_sub,
+                   int n_iter, double* c, double* obj_hist);
 double orc_nll_grad(const orc_geom* g, int nE, const double* I0, const double* mu,
                     const double* d, const unsigned char* mask, const double* c,
                     double* grad);

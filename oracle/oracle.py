@@ -13,6 +13,8 @@ Each function mirrors one step of the DEAM hot path:
     step_vjp     vector-Jacobian product of one iteration (chain rule through
                  the update, the backprojection, the weights and Eq. 8)
     metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
+    iterate_os   ordered subsets of views: per epoch one DEAM step per
+                 interleaved view subset, backprojecting only that subset
     fair, penalty, update_pen, iterate_pen
                  the penalised iteration: potential of Eq. 7 (the convex
                  "fair" reading), penalty of Eq. 6, and the decoupled
@@ -126,6 +128,9 @@ def _setup(L):
     L.orc_iterate_pen.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_double,
                                   C.c_double, C.c_int, d1, C.c_void_p]
     L.orc_iterate_pen.restype = C.c_int
+    L.orc_iterate_os.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, C.c_int, d1,
+                                 C.c_void_p]
+    L.orc_iterate_os.restype = C.c_int
     return L
 
 
@@ -322,4 +327,18 @@ def iterate_pen(g, I0, mu, d, mask, Z, lam, delta, c0, n_iter):
                                hist.ctypes.data_as(C.c_void_p))
     if rc != 0:
         raise MemoryError("oracle iterate_pen allocation failed")
+    return c, hist[:n_iter]
+
+
+def iterate_os(g, I0, mu, d, mask, Z, c0, n_sub, n_iter):
+    """n_iter epochs of ordered-subset DEAM with n_sub interleaved view
+    subsets; returns (c, masked I-divergence at the start of each epoch)."""
+    c = _f64(c0).copy()
+    hist = np.zeros(max(n_iter, 1))
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().orc_iterate_os(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                              _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
+                              int(n_sub), n_iter, c.reshape(-1), hist.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle iterate_os failed")
     return c, hist[:n_iter]

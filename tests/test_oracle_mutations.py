@@ -12,6 +12,7 @@ import tests.test_oracle_deam as D
 import tests.test_oracle_geometry as Gm
 import tests.test_oracle_unrolled as U
 import tests.test_oracle_penalty as Pn
+import tests.test_oracle_os as Os
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "deam_oracle.c")
@@ -63,6 +64,9 @@ MUTATIONS = {
     "pen_bisection_side": ("if (f > 0.0) hi = mid;", "if (f < 0.0) hi = mid;"),
     "pen_skipped_voxel": ("if (!(bt > 0.0 && bh > 0.0)) return ck;",
                           "if (!(bt > 0.0 && bh > 0.0)) return 0.0;"),
+    "os_subset_order": ("if ((y / per_view) % n_sub != s)", "if ((y / per_view) % n_sub != (s + 1) % n_sub)"),
+    "os_no_restriction": ("if ((y / per_view) % n_sub != s)", "if (0)"),
+    "os_history_at_last_subset": ("if (s == 0 && obj_hist) obj_hist[k]", "if (obj_hist) obj_hist[k]"),
     "pen_history_without_penalty": (
         "obj_hist[k] = orc_sum(R, obj) + orc_penalty(g, c, lambda, delta);",
         "obj_hist[k] = orc_sum(R, obj);"),
@@ -93,6 +97,8 @@ PINS = [
     lambda o: Pn.test_update_pen_quadratic_limit_lambert_w(o, Pn.small_box3d),
     lambda o: Pn.test_update_pen_minimises_voxel_surrogate(o, Pn.small_fan, 5e5, 0.002),
     lambda o: Pn.test_penalised_objective_decreases(o, 2e5, 0.005),
+    lambda o: Os.test_one_subset_is_deam(o),
+    lambda o: Os.test_subset_step_is_deam_on_the_subset_scan(o, 3),
 ]
 
 
