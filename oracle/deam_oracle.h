@@ -61,6 +61,10 @@ int orc_iterate_pen(const orc_geom* g, int nE, const double* I0, const double* m
 int orc_iterate_os(const orc_geom* g, int nE, const double* I0, const double* mu,
                    const double* d, const unsigned char* mask, const double Z[2], int n_sub,
                    int n_iter, double* c, double* obj_hist);
+int orc_iterate_dual(const orc_geom* const g[2], int nE, const double* I0, const double* mu,
+                     const double* const d[2], const unsigned char* const mask[2],
+                     const double Z[2], int n_iter, double* c, double* obj_hist);
+void orc_dilate_mask(const orc_geom* g, const unsigned char* mask, int radius, unsigned char* out);
 double orc_nll_grad(const orc_geom* g, int nE, const double* I0, const double* mu,
                     const double* d, const unsigned char* mask, const double* c,
                     double* grad);

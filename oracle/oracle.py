@@ -13,6 +13,8 @@ Each function mirrors one step of the DEAM hot path:
     step_vjp     vector-Jacobian product of one iteration (chain rule through
                  the update, the backprojection, the weights and Eq. 8)
     metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
+    iterate_dual separate system operators and traces for the two scans
+    dilate_mask  trace dilation along the channels
     iterate_os   ordered subsets of views: per epoch one DEAM step per
                  interleaved view subset, backprojecting only that subset
     fair, penalty, update_pen, iterate_pen
@@ -131,6 +133,10 @@ def _setup(L):
     L.orc_iterate_os.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, C.c_int, d1,
                                  C.c_void_p]
     L.orc_iterate_os.restype = C.c_int
+    L.orc_iterate_dual.argtypes = [C.c_void_p, C.c_int, d1, d1,
+                                   C.c_void_p, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
+    L.orc_iterate_dual.restype = C.c_int
+    L.orc_dilate_mask.argtypes = [G, u1, C.c_int, u1]
     return L
 
 
@@ -342,3 +348,30 @@ def iterate_os(g, I0, mu, d, mask, Z, c0, n_sub, n_iter):
     if rc != 0:
         raise MemoryError("oracle iterate_os failed")
     return c, hist[:n_iter]
+
+
+def iterate_dual(geoms, I0, mu, ds, masks, Z, c0, n_iter):
+    """DEAM with one geometry, counts and trace per scan: geoms, ds, masks are
+    pairs (low, high); ds[j] has shape (R_j,).  Returns (c, history of the sum
+    of the two masked I-divergences)."""
+    c = _f64(c0).copy()
+    hist = np.zeros(max(n_iter, 1))
+    gs = [geom_struct(g) for g in geoms]
+    gp = (C.c_void_p * 2)(*[C.cast(C.pointer(x), C.c_void_p) for x in gs])
+    dk = [_f64(x).reshape(-1) for x in ds]
+    dp = (C.c_void_p * 2)(*[x.ctypes.data_as(C.c_void_p) for x in dk])
+    mk = [None if m is None else np.ascontiguousarray(m, dtype=np.uint8).reshape(-1) for m in masks]
+    mp = (C.c_void_p * 2)(*[None if m is None else m.ctypes.data_as(C.c_void_p) for m in mk])
+    rc = lib().orc_iterate_dual(C.cast(gp, C.c_void_p), I0.shape[-1], _f64(I0).reshape(-1),
+                                _f64(mu).reshape(-1), C.cast(dp, C.c_void_p), C.cast(mp, C.c_void_p),
+                                _f64(Z), n_iter, c.reshape(-1), hist.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle iterate_dual failed")
+    return c, hist[:n_iter]
+
+
+def dilate_mask(g, mask, radius):
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    out = np.zeros_like(m)
+    lib().orc_dilate_mask(C.byref(geom_struct(g)), m, int(radius), out)
+    return out

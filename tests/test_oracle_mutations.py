@@ -13,6 +13,7 @@ import tests.test_oracle_geometry as Gm
 import tests.test_oracle_unrolled as U
 import tests.test_oracle_penalty as Pn
 import tests.test_oracle_os as Os
+import tests.test_oracle_dual as Du
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "deam_oracle.c")
@@ -64,6 +65,12 @@ MUTATIONS = {
     "pen_bisection_side": ("if (f > 0.0) hi = mid;", "if (f < 0.0) hi = mid;"),
     "pen_skipped_voxel": ("if (!(bt > 0.0 && bh > 0.0)) return ck;",
                           "if (!(bt > 0.0 && bh > 0.0)) return 0.0;"),
+    "dual_both_spectra_in_low_scan": ("I0j[e] = j == 0 ? I0[e] : 0.0;", "I0j[e] = I0[e];"),
+    "dual_last_scan_only": ("for (long x = 0; x < 4 * V; ++x) b[x] += bs[x];",
+                            "for (long x = 0; x < 4 * V; ++x) b[x] = bs[x];"),
+    "dual_counts_slot": ("memcpy(dd + (long)j * R[j], d[j],", "memcpy(dd, d[j],"),
+    "dilate_one_sided": ("for (long q = k - radius; q <= k + radius; ++q)",
+                         "for (long q = k; q <= k + radius; ++q)"),
     "os_subset_order": ("if ((y / per_view) % n_sub != s)", "if ((y / per_view) % n_sub != (s + 1) % n_sub)"),
     "os_no_restriction": ("if ((y / per_view) % n_sub != s)", "if (0)"),
     "os_history_at_last_subset": ("if (s == 0 && obj_hist) obj_hist[k]", "if (obj_hist) obj_hist[k]"),
@@ -99,6 +106,8 @@ PINS = [
     lambda o: Pn.test_penalised_objective_decreases(o, 2e5, 0.005),
     lambda o: Os.test_one_subset_is_deam(o),
     lambda o: Os.test_subset_step_is_deam_on_the_subset_scan(o, 3),
+    lambda o: Du.test_same_scans_are_deam(o),
+    lambda o: Du.test_dilate_mask(o),
 ]
 
 
