@@ -192,6 +192,21 @@ int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const
                        const double* Z, int32_t n_iter, double* obj_hist, void* ws,
                        size_t ws_bytes, void* stream, float* kernel_ms);
 
+/* Ordered-subset DEAM: n_iter epochs; the views are split into n_sub
+ * interleaved subsets (view v belongs to subset v mod n_sub), and an epoch
+ * runs one DEAM step per subset s = 0, 1, ..., n_sub - 1 using only that
+ * subset's rays (forward projection, poly-mean and backprojection walk its
+ * views alone; the update is deam_update's).  Each step costs about 1/n_sub
+ * of an iteration and moves about as far as a full one early on.  n_sub = 1
+ * is deam_iterate.  1 <= n_sub <= n_views.
+ *   obj_hist  device [n_iter] double or NULL: masked I-divergence at the
+ *             iterate entering each epoch (costs one extra all-view
+ *             projection per epoch when requested).
+ * Other arguments as deam_iterate.  Workspace: deam_workspace_size(DEAM_OP_ITERATE). */
+int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                    const double* Z, int32_t n_sub, int32_t n_iter, double* obj_hist, void* ws,
+                    size_t ws_bytes, void* stream);
+
 /* Vector-Jacobian product of one DEAM iteration (the differentiable form of
  * deam_iterate, for losses on the reconstructed image): with
  * Phi(c) = c - ln(b~(c) / b^(c)) / Z (the update of deam_update, c unchanged

@@ -25,7 +25,7 @@ EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_wor
            "deam_metal_trace", "deam_forward", "deam_poly_mean", "deam_backproject",
            "deam_update", "deam_iterate", "deam_iterate_timed", "deam_iterate_vjp",
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
-           "deam_fbp", "deam_nmar", "deam_mar_init", "deam_last_error")
+           "deam_fbp", "deam_nmar", "deam_mar_init", "deam_iterate_os", "deam_last_error")
 
 
 class DeamGeometry(C.Structure):
@@ -81,6 +81,7 @@ def load():
         "deam_fbp": [vp, vp, i32, vp, vp, sz, vp],
         "deam_nmar": [vp, vp, vp, vp, dp, vp, vp],
         "deam_mar_init": [vp, vp, C.POINTER(DeamMarParams), vp, vp, vp, vp, sz, vp],
+        "deam_iterate_os": [vp, vp, vp, vp, vp, i32, i32, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

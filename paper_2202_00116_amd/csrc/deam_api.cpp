@@ -383,6 +383,9 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.n_views = g.n_views;
   G.n_rows = g.n_rows;
   G.n_cols = g.n_cols;
+  G.voff = 0;
+  G.vsub = 1;
+  G.nvl = g.n_views;
   G.dx = g.dx;
   G.dy = g.dy;
   G.dz = g.dz;
@@ -780,6 +783,62 @@ int deam_mar_init(const deam_plan* plan, const float* d, const deam_mar_params* 
   HIP_TRY(deam::launch_nmar(plan, w + L.p, mask, w + L.pp, prm->eps, w + L.pc, st));
   HIP_TRY(deam::launch_fbp(plan, w + L.pc, 2, w + L.q, w + L.mu1, st));
   HIP_TRY(deam::launch_decompose(plan, w + L.mu1, c64, st));
+  return ok();
+}
+
+// A view of the plan restricted to the ordered subset s of n_sub: views
+// s, s + n_sub, s + 2 n_sub, ...  (same tables and buffers; only the walked
+// views and the grid sizes change).
+static deam_plan subset_plan(const deam_plan* p, int n_sub, int s) {
+  deam_plan q = *p;
+  q.gd.voff = s;
+  q.gd.vsub = n_sub;
+  q.gd.nvl = (p->gd.n_views - s + n_sub - 1) / n_sub;
+  const int64_t rl = (int64_t)q.gd.nvl * p->gd.n_rows * p->gd.n_cols;
+  q.ray_blocks = (rl + deam::kFpBlock - 1) / deam::kFpBlock;
+  if (p->gd.is3d) {
+    const int rg = p->precision == DEAM_PREC_FP64 ? deam::fp3_rows<double>() : deam::fp3_rows<float>();
+    q.fp_blocks = deam::fp3_blocks(q.gd.nvl, p->gd.n_rows, p->gd.n_cols, rg);
+  } else {
+    q.fp_blocks = q.ray_blocks;
+  }
+  return q;
+}
+
+int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
+                    const double* Z, int32_t n_sub, int32_t n_iter, double* obj_hist, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!c64 || !d || !Z) return fail(DEAM_ERR_NULL, "c64, d or Z is NULL");
+  if (n_iter < 0) return fail(DEAM_ERR_VALUE, "n_iter must be >= 0");
+  if (n_sub < 1 || n_sub > plan->gd.n_views)
+    return fail(DEAM_ERR_VALUE, "n_sub must be in [1, n_views] (got %d)", n_sub);
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  deam::WsLayout L;
+  if (int rc = check_ws(plan, DEAM_OP_ITERATE, ws, ws_bytes, L)) return rc;
+  char* w = (char*)ws;
+  hipStream_t st = (hipStream_t)stream;
+  void* cpy = w + L.cp_y;
+  void* cpx = w + L.cp_x;
+  uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  double* partial = (double*)(w + L.partial);
+  HIP_TRY(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
+  HIP_TRY(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
+  for (int k = 0; k < n_iter; ++k) {
+    if (obj_hist) {  // the objective needs every view at the epoch's iterate
+      HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+      HIP_TRY(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
+      HIP_TRY(deam::launch_reduce(partial, plan->fp_blocks, obj_hist + k, st));
+    }
+    for (int s = 0; s < n_sub; ++s) {
+      const deam_plan sub = subset_plan(plan, n_sub, s);
+      HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+      HIP_TRY(deam::launch_fp_poly(&sub, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
+      HIP_TRY(deam::launch_backproject(&sub, w + L.w, 4, true, wmax, w + L.b, st));
+      HIP_TRY(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
+    }
+  }
   return ok();
 }
 

@@ -29,6 +29,9 @@ struct GeomDev {
   int is3d;
   int nx, ny, nz;
   int n_views, n_rows, n_cols;
+  // views walked by the projectors and the backprojector: v = voff + vsub * i,
+  // i < nvl (all views: 0, 1, n_views; an ordered subset otherwise)
+  int voff, vsub, nvl;
   double dx, dy, dz;
   double x0, y0, z0;            // grid corner (mm)
   double sid, sdd, dgamma, kc;  // kc = (n_cols-1)/2 + col_offset

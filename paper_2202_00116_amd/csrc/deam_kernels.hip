@@ -581,15 +581,18 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
     double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
     uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t ray = (int64_t)lb * kFpBlock + threadIdx.x;
-  const bool active = ray < G.R;
+  // rays of the walked views, channel fastest; `ray` is the index in the
+  // full sinogram
+  const int64_t lray = (int64_t)lb * kFpBlock + threadIdx.x;
+  const bool active = lray < (int64_t)G.nvl * G.n_rows * G.n_cols;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
   {
-    const int64_t ra = active ? ray : 0;
+    const int64_t ra = active ? lray : 0;
     const int k = (int)(ra % G.n_cols);
     const int rv = (int)(ra / G.n_cols);
-    const int r = rv % G.n_rows, v = rv / G.n_rows;
+    const int r = rv % G.n_rows, v = G.voff + G.vsub * (rv / G.n_rows);
+    const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
     T l1, l2;
     const RayXY<T>* rays = (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
     // all lanes of the wave take part in the walk (lanes past the last ray idle)
@@ -641,11 +644,12 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
   constexpr uint32_t E = sizeof(T2);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int NKB = (G.n_cols + 63) >> 6;                           // channel blocks of 64
-  const int NVB = (G.n_views + kFp3Views - 1) / kFp3Views;        // view blocks
+  const int NVB = (G.nvl + kFp3Views - 1) / kFp3Views;            // view blocks
   const int vb = lb % NVB, kb = (lb / NVB) % NKB, g = lb / (NVB * NKB);
-  const int v = vb * kFp3Views + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int vi = vb * kFp3Views + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int k = kb * 64 + (int)(threadIdx.x & 63);
-  const bool valid = v < G.n_views && k < G.n_cols;
+  const bool valid = vi < G.nvl && k < G.n_cols;
+  const int v = G.voff + G.vsub * min(vi, G.nvl - 1);           // a walked view
   const int r0 = g * RG;
   const RayXY<T>* __restrict__ rays =
       (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
@@ -957,9 +961,9 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
   static_assert(kViewBatch % 64 == 0, "the prefix sum runs over whole waves of views");
   for (int i = threadIdx.x; i < 4 * kViewBatch; i += blockDim.x) {
     const int j = i >> 2, cn = i & 3;
-    const int v = vb0 + j;
+    const int v = G.voff + G.vsub * (vb0 + j);
     float kap = 0.f;
-    if (v < G.n_views) {
+    if (vb0 + j < G.nvl) {
       const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
       const double px = (cn & 1) ? X1 : X0, py = (cn & 2) ? Y1 : Y0;
       const double qx = px - G.sid * cb, qy = py - G.sid * sb;
@@ -971,9 +975,9 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
   __syncthreads();
   // channel and row ranges of each view
   for (int j = threadIdx.x; j < kViewBatch; j += blockDim.x) {
-    const int v = vb0 + j;
+    const int v = G.voff + G.vsub * (vb0 + j);
     int kl = 0, nk = 0, rl = 0, nr = 0;
-    if (v < G.n_views) {
+    if (vb0 + j < G.nvl) {
       const float kmn = fminf(fminf(s_kap[j][0], s_kap[j][1]), fminf(s_kap[j][2], s_kap[j][3]));
       const float kmx = fmaxf(fmaxf(s_kap[j][0], s_kap[j][1]), fmaxf(s_kap[j][2], s_kap[j][3]));
       kl = max((int)ceilf(kmn - 0.01f), 0);
@@ -1080,7 +1084,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
 
   // h1 bounds max_x sum_y h(x,y) over all views; a batch of kViewBatch views
   // contributes at most the fraction kViewBatch / n_views of it
-  const double hb = h1 * (double)min(kViewBatch, G.n_views) / (double)G.n_views;
+  const double hb = h1 * (double)min(kViewBatch, G.nvl) / (double)G.n_views;
   T scl[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -1101,7 +1105,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
   const double Z0 = G.z0 + tz0 * G.dz, Z1 = G.z0 + tz1 * G.dz;
   __syncthreads();
 
-  for (int vb0 = 0; vb0 < G.n_views; vb0 += kViewBatch) {
+  for (int vb0 = 0; vb0 < G.nvl; vb0 += kViewBatch) {
     cull_views<1>(G, vb0, X0, X1, Y0, Y1, Z0, Z1, s_kap, s_kl, s_nk, s_rl, s_nr, s_off);
     const int total = s_off[kViewBatch];
     for (int it = threadIdx.x; it < total; it += NT) {
@@ -1115,7 +1119,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
       const int rr = loc / nk;
       const int k = s_kl[j] + (loc - rr * nk);
       const int r = s_rl[j] + rr;
-      const int v = vb0 + j;
+      const int v = G.voff + G.vsub * (vb0 + j);
       Ray<T> ry;
       if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
       const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
@@ -1826,7 +1830,7 @@ static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, 
   const uint32_t xoff = (uint32_t)(((const T2*)cp_x) - ((const T2*)cp_y));
   if (p->gd.is3d) {
     constexpr int RG = fp3_rows<T>();
-    const dim3 grid3((unsigned)fp3_blocks(p->gd.n_views, p->gd.n_rows, p->gd.n_cols, RG));
+    const dim3 grid3((unsigned)fp3_blocks(p->gd.nvl, p->gd.n_rows, p->gd.n_cols, RG));
     hipLaunchKernelGGL((k_fp3<T, MODE, RG>), grid3, dim3(64 * kFp3Views), 0, st, p->gd,
                        (const T2*)cp_y, xoff,
                        eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);

@@ -235,6 +235,21 @@ class Plan:
                                        ws, n, _stream()))
         return c, M, mask
 
+    def iterate_os(self, c64, d, mask, Z, n_sub, n_iter, obj_hist=None):
+        """n_iter epochs of ordered-subset DEAM (n_sub interleaved view subsets)
+        in place on c64; obj_hist receives the masked I-divergence at the start
+        of each epoch."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        ws, n = self.workspace(L.OP_ITERATE)
+        L.check(self.lib.deam_iterate_os(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+                                         Zh.ctypes.data_as(C.c_void_p), int(n_sub), int(n_iter),
+                                         _ptr(obj_hist), ws, n, _stream()))
+        return c64
+
     def iterate_vjp(self, c64, d, mask, Z, G):
         """Vector-Jacobian product of one DEAM iteration at c64 for the upstream
         gradient G (both float64 (2, V)): returns (dPhi/dc)^T G."""
