@@ -126,6 +126,13 @@ int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes);
 int deam_metal_trace(const deam_plan* plan, const uint8_t* M, double t, uint8_t* mask,
                      double* T, void* ws, size_t ws_bytes, void* stream);
 
+/* Dilation of a trace along the detector channels (a safety margin around
+ * the corrupt rays): out[y] = 1 when a ray of the same view and detector row
+ * within `radius` channels of y has mask != 0.  0 <= radius <= n_cols;
+ * mask, out [R] uint8, not overlapping. */
+int deam_dilate_mask(const deam_plan* plan, const uint8_t* mask, int32_t radius, uint8_t* out,
+                     void* stream);
+
 /* Forward projection (the inner sum of Eq. 8): l[c][y] = sum_x h(x,y) c[c][x].
  *   c  [n_ch][V] real;  l [n_ch][R] real;  n_ch = 1 or 2.
  * Workspace: deam_workspace_size(DEAM_OP_FORWARD). */
@@ -191,6 +198,27 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
 int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
                        const double* Z, int32_t n_iter, double* obj_hist, void* ws,
                        size_t ws_bytes, void* stream, float* kernel_ms);
+
+/* DEAM with a system operator and a metal trace per scan (Section 2.1: the
+ * two scans may differ, e.g. by geometry or motion, and then need their own
+ * traces T_j).  Each scan has its own plan over the same image grid and
+ * precision: plan_lo created with the high-energy spectrum all zero and
+ * plan_hi with the low-energy spectrum all zero (DEAM_ERR_VALUE otherwise),
+ * so that each scan's energy sums and weights use its own spectrum only.
+ * b~ and b^ are the sums of the two scans' backprojections; the update is
+ * deam_update's.
+ *   d_lo [2][R_lo], d_hi [2][R_hi] float: channel 0 of d_lo holds the
+ *       low-energy counts and channel 1 of d_hi the high-energy counts; the
+ *       other channel is read but does not enter (its expected counts are 0);
+ *   mask_lo [R_lo], mask_hi [R_hi] uint8 or NULL: each scan's trace;
+ *   obj_hist  device [n_iter] double or NULL: the sum of the two masked
+ *             I-divergences at the iterate entering each iteration.
+ * Workspace: deam_dual_workspace_size bytes. */
+int deam_dual_workspace_size(const deam_plan* plan_lo, const deam_plan* plan_hi, size_t* bytes);
+int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double* c64,
+                      const float* d_lo, const uint8_t* mask_lo, const float* d_hi,
+                      const uint8_t* mask_hi, const double* Z, int32_t n_iter, double* obj_hist,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Ordered-subset DEAM: n_iter epochs; the views are split into n_sub
  * interleaved subsets (view v belongs to subset v mod n_sub), and an epoch

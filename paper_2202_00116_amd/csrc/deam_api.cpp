@@ -724,6 +724,18 @@ static int check_fbp(const deam_plan* plan) {
   return DEAM_OK;
 }
 
+int deam_dilate_mask(const deam_plan* plan, const uint8_t* mask, int32_t radius, uint8_t* out,
+                     void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!mask || !out) return fail(DEAM_ERR_NULL, "mask or out is NULL");
+  if (radius < 0 || radius > plan->gd.n_cols) return fail(DEAM_ERR_VALUE, "radius out of range");
+  const size_t nb = (size_t)plan->gd.R;
+  if ((const char*)mask < (const char*)out + nb && (const char*)out < (const char*)mask + nb)
+    return fail(DEAM_ERR_VALUE, "out overlaps mask");
+  HIP_TRY(deam::launch_dilate(plan, mask, radius, out, (hipStream_t)stream));
+  return ok();
+}
+
 int deam_fbp(const deam_plan* plan, const void* p, int32_t n_ch, void* img, void* ws,
              size_t ws_bytes, void* stream) {
   if (int rc = check_plan(plan)) return rc;
@@ -838,6 +850,77 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
       HIP_TRY(deam::launch_backproject(&sub, w + L.w, 4, true, wmax, w + L.b, st));
       HIP_TRY(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
     }
+  }
+  return ok();
+}
+
+static int check_dual(const deam_plan* lo, const deam_plan* hi) {
+  if (int rc = check_plan(lo)) return rc;
+  if (int rc = check_plan(hi)) return rc;
+  if (lo->precision != hi->precision) return fail(DEAM_ERR_VALUE, "the two plans differ in precision");
+  const deam_geometry &a = lo->g, &b = hi->g;
+  if (a.kind != b.kind || lo->gd.nx != hi->gd.nx || lo->gd.ny != hi->gd.ny ||
+      lo->gd.nz != hi->gd.nz || a.dx != b.dx || a.dy != b.dy || (a.kind == DEAM_HELICAL3D && a.dz != b.dz))
+    return fail(DEAM_ERR_VALUE, "the two plans must share the image grid");
+  if (!(lo->i0sum[0] > 0.0 && lo->i0sum[1] == 0.0 && hi->i0sum[0] == 0.0 && hi->i0sum[1] > 0.0))
+    return fail(DEAM_ERR_VALUE,
+                "plan_lo must carry only the low spectrum and plan_hi only the high spectrum");
+  return DEAM_OK;
+}
+
+int deam_dual_workspace_size(const deam_plan* plan_lo, const deam_plan* plan_hi, size_t* bytes) {
+  if (!bytes) return fail(DEAM_ERR_NULL, "bytes is NULL");
+  if (int rc = check_dual(plan_lo, plan_hi)) return rc;
+  *bytes = align256(deam::workspace_layout(plan_lo, DEAM_OP_ITERATE).total) +
+           deam::workspace_layout(plan_hi, DEAM_OP_ITERATE).total;
+  return ok();
+}
+
+int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double* c64,
+                      const float* d_lo, const uint8_t* mask_lo, const float* d_hi,
+                      const uint8_t* mask_hi, const double* Z, int32_t n_iter, double* obj_hist,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_dual(plan_lo, plan_hi)) return rc;
+  if (!c64 || !d_lo || !d_hi || !Z) return fail(DEAM_ERR_NULL, "c64, d_lo, d_hi or Z is NULL");
+  if (n_iter < 0) return fail(DEAM_ERR_VALUE, "n_iter must be >= 0");
+  if (!(Z[0] > 0.0 && Z[1] > 0.0 && std::isfinite(Z[0]) && std::isfinite(Z[1])))
+    return fail(DEAM_ERR_VALUE, "Z must be positive and finite");
+  const deam::WsLayout LA = deam::workspace_layout(plan_lo, DEAM_OP_ITERATE);
+  const deam::WsLayout LB = deam::workspace_layout(plan_hi, DEAM_OP_ITERATE);
+  const size_t offb = align256(LA.total);
+  if (!ws) return fail(DEAM_ERR_NULL, "workspace is NULL");
+  if (ws_bytes < offb + LB.total)
+    return fail(DEAM_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, offb + LB.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(DEAM_ERR_VALUE, "workspace must be 256-byte aligned");
+  char* wa = (char*)ws;
+  char* wb = wa + offb;
+  hipStream_t st = (hipStream_t)stream;
+  // one packed copy of c serves both scans (same image grid)
+  void* cpy = wa + LA.cp_y;
+  void* cpx = wa + LA.cp_x;
+  uint32_t* wmax_a = (uint32_t*)(wa + LA.wmax);
+  uint32_t* wmax_b = (uint32_t*)(wb + LB.wmax);
+  double* part_a = (double*)(wa + LA.partial);
+  double* part_b = (double*)(wb + LB.partial);
+  double* two = (double*)(wa + LA.scratch);
+  HIP_TRY(deam::launch_update(plan_lo, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
+  HIP_TRY(deam::launch_zero_tail(plan_lo, cpx, plan_lo->precision == DEAM_PREC_FP64, st));
+  for (int k = 0; k < n_iter; ++k) {
+    HIP_TRY(deam::launch_fill_u32(wmax_a, 0u, 16, st));
+    HIP_TRY(deam::launch_fill_u32(wmax_b, 0u, 16, st));
+    HIP_TRY(deam::launch_fp_poly(plan_lo, cpy, cpx, d_lo, mask_lo, deam::PM_AM, wa + LA.w, part_a,
+                                 wmax_a, st));
+    HIP_TRY(deam::launch_fp_poly(plan_hi, cpy, cpx, d_hi, mask_hi, deam::PM_AM, wb + LB.w, part_b,
+                                 wmax_b, st));
+    if (obj_hist) {
+      HIP_TRY(deam::launch_reduce(part_a, plan_lo->fp_blocks, two, st));
+      HIP_TRY(deam::launch_reduce(part_b, plan_hi->fp_blocks, two + 1, st));
+      HIP_TRY(deam::launch_reduce(two, 2, obj_hist + k, st));
+    }
+    HIP_TRY(deam::launch_backproject(plan_lo, wa + LA.w, 4, true, wmax_a, wa + LA.b, st));
+    HIP_TRY(deam::launch_backproject(plan_hi, wb + LB.w, 4, true, wmax_b, wb + LB.b, st));
+    HIP_TRY(deam::launch_update(plan_lo, c64, wa + LA.b, Z[0], Z[1], nullptr, cpy, cpx, st,
+                                wb + LB.b));
   }
   return ok();
 }

@@ -168,8 +168,10 @@ hipError_t launch_step_u(const deam_plan* p, const double* G, const void* b, dou
 // out = G + bl (double [2][V])
 hipError_t launch_add_g(const deam_plan* p, const double* G, const void* bl, double* out,
                         hipStream_t st);
+// b2 (or NULL) is added to b: the backprojections of a second scan
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
-                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st);
+                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st,
+                         const void* b2 = nullptr);
 // penalised update (Eqs. 6-7): c64 <- argmin of the decoupled per-voxel
 // surrogate around c_prev (distinct from c64), same outputs as launch_update
 hipError_t launch_update_pen(const deam_plan* p, const double* c_prev, double* c64, const void* b,
@@ -189,6 +191,8 @@ hipError_t launch_nmar(const deam_plan* p, const void* sino, const uint8_t* mask
 hipError_t launch_mar_classes(const deam_plan* p, const void* mu0, const double water[2],
                               double fa, double fb, double fm, uint8_t* M, void* prior,
                               hipStream_t st);
+hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, uint8_t* out,
+                         hipStream_t st);
 hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hipStream_t st);
 
 WsLayout workspace_layout(const deam_plan* p, int op);

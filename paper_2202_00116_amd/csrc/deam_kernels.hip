@@ -1337,9 +1337,11 @@ __global__ __launch_bounds__(256) void k_add_g(int64_t n, const double* __restri
 // ---------------------------------------------------------------------------
 // Update and packing (32x32 tiles, LDS transpose for the x-major copy)
 // ---------------------------------------------------------------------------
+// b2 (or NULL): a second set of backprojections added to b (two scans).
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(GeomDev G, double* __restrict__ c64,
-                                                const T* __restrict__ b, double iz1, double iz2,
+                                                const T* __restrict__ b, const T* __restrict__ b2,
+                                                double iz1, double iz2,
                                                 T* __restrict__ c_proj,
                                                 typename Vec2<T>::type* __restrict__ cpy,
                                                 typename Vec2<T>::type* __restrict__ cpx) {
@@ -1355,8 +1357,14 @@ __global__ __launch_bounds__(256) void k_update(GeomDev G, double* __restrict__ 
       const int64_t idx = ((int64_t)z * G.ny + iy) * G.nx + ix;
       double c1 = c64[idx], c2 = c64[V + idx];
       if (b) {
-        const double bt1 = (double)b[idx], bt2 = (double)b[V + idx];
-        const double bh1 = (double)b[2 * V + idx], bh2 = (double)b[3 * V + idx];
+        double bt1 = (double)b[idx], bt2 = (double)b[V + idx];
+        double bh1 = (double)b[2 * V + idx], bh2 = (double)b[3 * V + idx];
+        if (b2) {
+          bt1 += (double)b2[idx];
+          bt2 += (double)b2[V + idx];
+          bh1 += (double)b2[2 * V + idx];
+          bh2 += (double)b2[3 * V + idx];
+        }
         if (bt1 > 0.0 && bh1 > 0.0) c1 -= log(bt1 / bh1) * iz1;
         if (bt2 > 0.0 && bh2 > 0.0) c2 -= log(bt2 / bh2) * iz2;
         c64[idx] = c1;
@@ -1781,6 +1789,21 @@ __global__ __launch_bounds__(256) void k_decompose(int64_t V, const T* __restric
   c[V + x] = a10 * ml + a11 * mh;
 }
 
+// Trace dilation along the channels: out[y] = 1 when a ray of the same view
+// and row within `radius` channels of y is in mask.
+__global__ __launch_bounds__(256) void k_dilate(int64_t R, int n_cols, int radius,
+                                                const uint8_t* __restrict__ mask,
+                                                uint8_t* __restrict__ out) {
+  const int64_t y = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (y >= R) return;
+  const int k = (int)(y % n_cols);
+  const int64_t row = y - k;
+  const int lo = max(k - radius, 0), hi = min(k + radius, n_cols - 1);
+  uint8_t m = 0;
+  for (int q = lo; q <= hi; ++q) m |= mask[row + q];
+  out[y] = m ? 1 : 0;
+}
+
 inline dim3 image_grid(const deam_plan* p) {
   return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
 }
@@ -1993,15 +2016,15 @@ hipError_t launch_add_g(const deam_plan* p, const double* G, const void* bl, dou
 }
 
 hipError_t launch_update(const deam_plan* p, double* c64, const void* b, double z1, double z2,
-                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st) {
+                         void* c_proj, void* cp_y, void* cp_x, hipStream_t st, const void* b2) {
   if (p->precision == DEAM_PREC_FP64)
     hipLaunchKernelGGL(k_update<double>, image_grid(p), dim3(256), 0, st, p->gd, c64,
-                       (const double*)b, 1.0 / z1, 1.0 / z2, (double*)c_proj, (double2*)cp_y,
-                       (double2*)cp_x);
+                       (const double*)b, (const double*)b2, 1.0 / z1, 1.0 / z2, (double*)c_proj,
+                       (double2*)cp_y, (double2*)cp_x);
   else
     hipLaunchKernelGGL(k_update<float>, image_grid(p), dim3(256), 0, st, p->gd, c64,
-                       (const float*)b, 1.0 / z1, 1.0 / z2, (float*)c_proj, (float2*)cp_y,
-                       (float2*)cp_x);
+                       (const float*)b, (const float*)b2, 1.0 / z1, 1.0 / z2, (float*)c_proj,
+                       (float2*)cp_y, (float2*)cp_x);
   return hipGetLastError();
 }
 
@@ -2142,6 +2165,15 @@ hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hip
   return hipGetLastError();
 }
 
+hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, uint8_t* out,
+                         hipStream_t st) {
+  const int64_t R = p->gd.R;
+  hipLaunchKernelGGL(k_dilate, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, R,
+                     p->gd.n_cols, radius, mask, out);
+  return hipGetLastError();
+}
+
 }  // namespace deam
+
 
 

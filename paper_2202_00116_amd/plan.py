@@ -199,6 +199,13 @@ class Plan:
                                                 _stream()))
         return c64
 
+    def dilate_mask(self, mask, radius):
+        """Trace dilated by `radius` channels (same view and row)."""
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        out = torch.empty_like(mask)
+        L.check(self.lib.deam_dilate_mask(self._p, _ptr(mask), int(radius), _ptr(out), _stream()))
+        return out
+
     def fbp(self, p):
         """Fan-beam FBP of line integrals p (n_ch, R), n_ch in {1, 2}: (n_ch, V)."""
         n_ch = p.shape[0]
@@ -279,3 +286,32 @@ class Plan:
                                             Zh.ctypes.data_as(C.c_void_p), int(n_iter),
                                             _ptr(obj_hist), ws, n, _stream(), ms))
         return dict(fp_poly=ms[0], backproject=ms[1], update=ms[2], loop=ms[3])
+
+
+def iterate_dual(plan_lo, plan_hi, c64, d_lo, mask_lo, d_hi, mask_hi, Z, n_iter, obj_hist=None):
+    """DEAM with a system operator and a trace per scan (deam_iterate_dual).
+    plan_lo / plan_hi carry only their own spectrum; d_lo, d_hi are (2, R_j)
+    float32 with the scan's counts in its own channel."""
+    lib = plan_lo.lib
+    plan_lo._check(c64, (2, plan_lo.V), torch.float64, "c64")
+    plan_lo._check(d_lo, (2, plan_lo.R), torch.float32, "d_lo")
+    plan_hi._check(d_hi, (2, plan_hi.R), torch.float32, "d_hi")
+    plan_lo._check(mask_lo, (plan_lo.R,), torch.uint8, "mask_lo")
+    plan_hi._check(mask_hi, (plan_hi.R,), torch.uint8, "mask_hi")
+    plan_lo._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+    n = C.c_size_t(0)
+    L.check(lib.deam_dual_workspace_size(plan_lo._p, plan_hi._p, C.byref(n)))
+    key = ("dual", id(plan_hi))
+    buf = plan_lo._ws.get(key)
+    if buf is None or buf[2] < n.value:      # cached on plan_lo, like its own workspaces
+        raw = torch.empty(int(n.value) + 256, dtype=torch.uint8, device=plan_lo.device)
+        plan_lo._ws[key] = (raw, (-raw.data_ptr()) % 256, int(n.value))
+        buf = plan_lo._ws[key]
+    raw, off, _ = buf
+    base = raw.data_ptr()
+    Zh = np.ascontiguousarray(Z, dtype=np.float64)
+    L.check(lib.deam_iterate_dual(plan_lo._p, plan_hi._p, _ptr(c64), _ptr(d_lo), _ptr(mask_lo),
+                                  _ptr(d_hi), _ptr(mask_hi), Zh.ctypes.data_as(C.c_void_p),
+                                  int(n_iter), _ptr(obj_hist), C.c_void_p(base + off),
+                                  int(n.value), _stream()))
+    return c64

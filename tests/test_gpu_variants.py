@@ -1,0 +1,106 @@
+"""Model variants on the GPU against the oracle: separate operators and
+traces for the low- and high-energy scans (deam_iterate_dual) and the trace
+dilation (deam_dilate_mask)."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import make_inputs
+from tests.test_oracle_dual import shifted_scan
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def _one_spectrum(I0, j):
+    out = np.zeros_like(I0)
+    out[j] = I0[j]
+    return out
+
+
+def _two_scans(orc, name):
+    from workloads.configs import expected_counts, phantom_for
+    inp = make_inputs(name)
+    gl = inp["geom"]
+    gh = shifted_scan(gl)
+    gbar = expected_counts(gh, phantom_for(name), inp["I0"])
+    dh = np.random.default_rng(97).poisson(gbar[1]).astype(np.float64)
+    ml = orc.metal_trace(gl, inp["metal"], inp["t"])[0]
+    mh = orc.metal_trace(gh, inp["metal"], inp["t"])[0]
+    return inp, gl, gh, dh, ml, mh
+
+
+@pytest.mark.parametrize("name,n", [("fan64", 10), ("helical_small", 4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_iterate_dual_matches_oracle(orc, name, n, prec, tol):
+    from paper_2202_00116_amd.plan import Plan, iterate_dual
+    inp, gl, gh, dh, ml, mh = _two_scans(orc, name)
+    ref, href = orc.iterate_dual((gl, gh), inp["I0"], inp["mu"], (inp["d"][0], dh), (ml, mh),
+                                 inp["Z"], inp["c0"], n)
+    plo = Plan(gl, _one_spectrum(inp["I0"], 0), inp["mu"], prec)
+    phi = Plan(gh, _one_spectrum(inp["I0"], 1), inp["mu"], prec)
+    M = torch.tensor(inp["metal"], device=DEV)
+    mlt, mht = plo.metal_trace(M, inp["t"]), phi.metal_trace(M, inp["t"])
+    assert np.array_equal(mlt.cpu().numpy(), ml) and np.array_equal(mht.cpu().numpy(), mh)
+    d_lo = torch.zeros((2, plo.R), dtype=torch.float32, device=DEV)
+    d_lo[0] = torch.tensor(inp["d"][0], device=DEV)
+    d_hi = torch.zeros((2, phi.R), dtype=torch.float32, device=DEV)
+    d_hi[1] = torch.tensor(dh, dtype=torch.float32, device=DEV)
+    c = torch.tensor(inp["c0"], device=DEV)
+    h = torch.zeros(n, dtype=torch.float64, device=DEV)
+    iterate_dual(plo, phi, c, d_lo, mlt, d_hi, mht, inp["Z"], n, h)
+    e = rel(c.cpu().numpy(), ref)
+    eh = float(np.abs(h.cpu().numpy() - href).max() / abs(href[0]))
+    print(f"{name} {prec} two scans, {n} it.: image rel {e:.3e}, objective rel {eh:.3e}")
+    assert e <= tol and eh <= tol
+    if prec == "fp64":
+        assert np.all(np.diff(h.cpu().numpy()) < 0)
+
+
+def test_iterate_dual_same_scans_is_iterate():
+    from paper_2202_00116_amd.plan import Plan, iterate_dual
+    inp = make_inputs("fan64")
+    g = inp["geom"]
+    plan = Plan(g, inp["I0"], inp["mu"], "fp64")
+    plo = Plan(g, _one_spectrum(inp["I0"], 0), inp["mu"], "fp64")
+    phi = Plan(g, _one_spectrum(inp["I0"], 1), inp["mu"], "fp64")
+    d = torch.tensor(inp["d"], device=DEV)
+    a = torch.tensor(inp["c0"], device=DEV)
+    b = a.clone()
+    plan.iterate(a, d, None, inp["Z"], 5)
+    iterate_dual(plo, phi, b, d, None, d, None, inp["Z"], 5)
+    assert (a - b).abs().max().item() <= 1e-12 * a.abs().max().item()
+
+
+def test_iterate_dual_rejects_mismatched_plans():
+    from paper_2202_00116_amd._lib import DeamError
+    from paper_2202_00116_amd.plan import Plan, iterate_dual
+    inp = make_inputs("fan64", with_data=False)
+    g = inp["geom"]
+    both = Plan(g, inp["I0"], inp["mu"], "mixed")
+    plo = Plan(g, _one_spectrum(inp["I0"], 0), inp["mu"], "mixed")
+    phi = Plan(g, _one_spectrum(inp["I0"], 1), inp["mu"], "mixed")
+    c = torch.zeros((2, plo.V), dtype=torch.float64, device=DEV)
+    d = torch.ones((2, plo.R), dtype=torch.float32, device=DEV)
+    for a, b in ((both, phi), (plo, both), (phi, plo)):
+        with pytest.raises(DeamError, match="VALUE"):
+            iterate_dual(a, b, c, d, None, d, None, inp["Z"], 1)
+
+
+@pytest.mark.parametrize("radius", [0, 1, 3, 17])
+def test_dilate_mask_matches_oracle(orc, radius):
+    from paper_2202_00116_amd.plan import Plan
+    inp = make_inputs("helical_small", with_data=False)
+    g = inp["geom"]
+    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
+    mask = orc.metal_trace(g, inp["metal"], inp["t"])[0]
+    rng = np.random.default_rng(99)
+    mask = mask | (rng.uniform(size=mask.shape) < 0.01).astype(np.uint8)
+    out = plan.dilate_mask(torch.tensor(mask, device=DEV), radius).cpu().numpy()
+    ref = orc.dilate_mask(g, mask, radius)
+    assert np.array_equal(out, ref)
+    assert out.sum() >= mask.sum()
