@@ -271,20 +271,28 @@ void orc_backproject(const orc_geom* g, int nch, const double* sino, double* img
 /* Per-ray polyenergetic mean with metal-trace substitution.                */
 /* ----------------------------------------------------------------------- */
 
-void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
-                   const double* l, const double* d, const unsigned char* mask,
-                   int mode, const double* v, double* w, double* gout, double* obj) {
+/* bt (or NULL): a bowtie filter, given as its path lengths (mm) in the two
+ * basis materials per detector channel, bt[i * n_cols + k]: ray y of channel
+ * k = y mod n_cols then sees the spectra I0_j(E) exp(-mu_1(E) bt_1k -
+ * mu_2(E) bt_2k) (energy and channel dependent I0_j(y,E) of Eq. 8). */
+static void poly_mean_impl(long R, int nE, const double* I0, const double* mu,
+                           const double* bt, int n_cols,
+                           const double* l, const double* d, const unsigned char* mask,
+                           int mode, const double* v, double* w, double* gout, double* obj) {
 #pragma omp parallel for schedule(static)
   for (long y = 0; y < R; ++y) {
     double l1 = l[y], l2 = l[R + y];
+    long kb = bt ? y % n_cols : 0;
     nsum gs[2] = {{0, 0}, {0, 0}};
     nsum as[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};   /* as[i][j] */
     nsum ms[2][3] = {{{0, 0}, {0, 0}, {0, 0}}, {{0, 0}, {0, 0}, {0, 0}}};  /* m_11, m_12, m_22 */
     for (int e = 0; e < nE; ++e) {
       double mu1 = mu[e], mu2 = mu[nE + e];
       double ex = exp(-(mu1 * l1 + mu2 * l2));
+      double fb = bt ? exp(-(mu1 * bt[kb] + mu2 * bt[n_cols + kb])) : 1.0;
       for (int j = 0; j < 2; ++j) {
         double q = I0[j * nE + e] * ex;                     /* q_j(y,E) */
+        if (bt) q = (I0[j * nE + e] * fb) * ex;             /* the ray's own spectrum */
         nadd(&gs[j], q);
         nadd(&as[0][j], mu1 * q);
         nadd(&as[1][j], mu2 * q);
@@ -366,6 +374,18 @@ void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
     if (gout) { gout[y] = gj[0]; gout[R + y] = gj[1]; }
     if (obj) obj[y] = term;
   }
+}
+
+void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
+                   const double* l, const double* d, const unsigned char* mask,
+                   int mode, const double* v, double* w, double* gout, double* obj) {
+  poly_mean_impl(R, nE, I0, mu, NULL, 0, l, d, mask, mode, v, w, gout, obj);
+}
+
+void orc_poly_mean_bt(long R, int nE, const double* I0, const double* mu, const double* bt,
+                      int n_cols, const double* l, const double* d, const unsigned char* mask,
+                      int mode, const double* v, double* w, double* gout, double* obj) {
+  poly_mean_impl(R, nE, I0, mu, bt, n_cols, l, d, mask, mode, v, w, gout, obj);
 }
 
 double orc_sum(long n, const double* x) {
@@ -745,4 +765,26 @@ void orc_dilate_mask(const orc_geom* g, const unsigned char* mask, int radius, u
       if (q >= 0 && q < g->n_cols && mask[row0 + q]) m = 1;
     out[y] = m;
   }
+}
+
+/* DEAM with a bowtie filter (see poly_mean_impl): n_iter iterations from c
+ * (in place); obj_hist[k] (or NULL) = masked I-divergence at c^k. */
+int orc_iterate_bt(const orc_geom* g, int nE, const double* I0, const double* mu,
+                   const double* bt, const double* d, const unsigned char* mask,
+                   const double Z[2], int n_iter, double* c, double* obj_hist) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
+  double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
+  double* obj = (double*)malloc(sizeof(double) * (size_t)R);
+  double* b = (double*)malloc(sizeof(double) * (size_t)(4 * V));
+  if (!l || !w || !obj || !b) { free(l); free(w); free(obj); free(b); return -1; }
+  for (int k = 0; k < n_iter; ++k) {
+    orc_forward(g, 2, c, l);
+    orc_poly_mean_bt(R, nE, I0, mu, bt, g->n_cols, l, d, mask, ORC_W_AM, NULL, w, NULL, obj);
+    if (obj_hist) obj_hist[k] = orc_sum(R, obj);
+    orc_backproject(g, 4, w, b);
+    orc_update(V, b, Z, c);
+  }
+  free(l); free(w); free(obj); free(b);
+  return 0;
 }

@@ -35,6 +35,12 @@ void orc_backproject(const orc_geom* g, int nch, const double* sino, double* img
 void orc_poly_mean(long R, int nE, const double* I0, const double* mu,
                    const double* l, const double* d, const unsigned char* mask,
                    int mode, const double* v, double* w, double* gout, double* obj);
+void orc_poly_mean_bt(long R, int nE, const double* I0, const double* mu, const double* bt,
+                      int n_cols, const double* l, const double* d, const unsigned char* mask,
+                      int mode, const double* v, double* w, double* gout, double* obj);
+int orc_iterate_bt(const orc_geom* g, int nE, const double* I0, const double* mu,
+                   const double* bt, const double* d, const unsigned char* mask,
+                   const double Z[2], int n_iter, double* c, double* obj_hist);
 double orc_sum(long n, const double* x);
 int orc_step_vjp(const orc_geom* g, int nE, const double* I0, const double* mu,
                  const double* d, const unsigned char* mask, const double Z[2],

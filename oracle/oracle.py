@@ -13,6 +13,8 @@ Each function mirrors one step of the DEAM hot path:
     step_vjp     vector-Jacobian product of one iteration (chain rule through
                  the update, the backprojection, the weights and Eq. 8)
     metal_trace  T = H M, mask = [T >= t]     (Eqs. 2-3)
+    poly_mean_bt, iterate_bt
+                 a bowtie filter: per-channel spectra I0_j(y,E)
     iterate_dual separate system operators and traces for the two scans
     dilate_mask  trace dilation along the channels
     iterate_os   ordered subsets of views: per epoch one DEAM step per
@@ -107,6 +109,10 @@ def _setup(L):
     L.orc_backproject.argtypes = [G, C.c_int, d1, d1]
     L.orc_poly_mean.argtypes = [C.c_long, C.c_int, d1, d1, d1, d1, C.c_void_p, C.c_int,
                                 C.c_void_p, d1, C.c_void_p, C.c_void_p]
+    L.orc_poly_mean_bt.argtypes = [C.c_long, C.c_int, d1, d1, d1, C.c_int, d1, d1, C.c_void_p,
+                                   C.c_int, C.c_void_p, d1, C.c_void_p, C.c_void_p]
+    L.orc_iterate_bt.argtypes = [G, C.c_int, d1, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
+    L.orc_iterate_bt.restype = C.c_int
     L.orc_sum.argtypes = [C.c_long, d1]
     L.orc_sum.restype = C.c_double
     L.orc_update.argtypes = [C.c_long, d1, d1, d1]
@@ -375,3 +381,35 @@ def dilate_mask(g, mask, radius):
     out = np.zeros_like(m)
     lib().orc_dilate_mask(C.byref(geom_struct(g)), m, int(radius), out)
     return out
+
+
+def poly_mean_bt(I0, mu, bt, l, d, mask=None, mode=W_AM, v=None):
+    """poly_mean with a bowtie: bt (2, n_cols) basis path lengths (mm) of the
+    filter per channel; ray y belongs to channel y mod n_cols."""
+    I0, mu, l, d, bt = _f64(I0), _f64(mu), _f64(l), _f64(d), _f64(bt)
+    R = l.shape[-1]
+    nE = I0.shape[-1]
+    nw = 4 if mode == W_AM else 2
+    w = np.zeros(nw * R)
+    g = np.zeros(2 * R)
+    obj = np.zeros(R)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    vv = None if v is None else _f64(v)
+    lib().orc_poly_mean_bt(R, nE, I0.reshape(-1), mu.reshape(-1), bt.reshape(-1), bt.shape[-1],
+                           l.reshape(-1), d.reshape(-1), _ptr(m), mode, _ptr(vv), w,
+                           g.ctypes.data_as(C.c_void_p), obj.ctypes.data_as(C.c_void_p))
+    return w.reshape(nw, R), g.reshape(2, R), obj
+
+
+def iterate_bt(g, I0, mu, bt, d, mask, Z, c0, n_iter):
+    """DEAM with a bowtie filter bt (2, n_cols)."""
+    c = _f64(c0).copy()
+    hist = np.zeros(max(n_iter, 1))
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rc = lib().orc_iterate_bt(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                              _f64(mu).reshape(-1), _f64(bt).reshape(-1), _f64(d).reshape(-1),
+                              _ptr(m), _f64(Z), n_iter, c.reshape(-1),
+                              hist.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise MemoryError("oracle iterate_bt failed")
+    return c, hist[:n_iter]

@@ -14,6 +14,7 @@ import tests.test_oracle_unrolled as U
 import tests.test_oracle_penalty as Pn
 import tests.test_oracle_os as Os
 import tests.test_oracle_dual as Du
+import tests.test_oracle_bowtie as Bt
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "deam_oracle.c")
@@ -65,6 +66,11 @@ MUTATIONS = {
     "pen_bisection_side": ("if (f > 0.0) hi = mid;", "if (f < 0.0) hi = mid;"),
     "pen_skipped_voxel": ("if (!(bt > 0.0 && bh > 0.0)) return ck;",
                           "if (!(bt > 0.0 && bh > 0.0)) return 0.0;"),
+    "bowtie_sign": ("double fb = bt ? exp(-(mu1 * bt[kb] + mu2 * bt[n_cols + kb])) : 1.0;",
+                    "double fb = bt ? exp(+(mu1 * bt[kb] + mu2 * bt[n_cols + kb])) : 1.0;"),
+    "bowtie_channel": ("long kb = bt ? y % n_cols : 0;", "long kb = bt ? (y / n_cols) % n_cols : 0;"),
+    "bowtie_basis_swap": ("exp(-(mu1 * bt[kb] + mu2 * bt[n_cols + kb]))",
+                          "exp(-(mu2 * bt[kb] + mu1 * bt[n_cols + kb]))"),
     "dual_both_spectra_in_low_scan": ("I0j[e] = j == 0 ? I0[e] : 0.0;", "I0j[e] = I0[e];"),
     "dual_last_scan_only": ("for (long x = 0; x < 4 * V; ++x) b[x] += bs[x];",
                             "for (long x = 0; x < 4 * V; ++x) b[x] = bs[x];"),
@@ -108,6 +114,7 @@ PINS = [
     lambda o: Os.test_subset_step_is_deam_on_the_subset_scan(o, 3),
     lambda o: Du.test_same_scans_are_deam(o),
     lambda o: Du.test_dilate_mask(o),
+    lambda o: Bt.test_filter_is_a_shift_of_the_line_integrals(o, "am"),
 ]
 
 

@@ -135,8 +135,20 @@ def _views_chunks(n_views, per):
     return [np.arange(a, min(a + per, n_views)) for a in range(0, n_views, per)]
 
 
-def expected_counts(geom, phantom, I0, threads=None):
-    """Expected counts (2, n_rays) of the continuous phantom, float64."""
+def bowtie(geom, b1_edge=25.0, b2_edge=2.0):
+    """A bowtie filter as its path lengths (mm) in the two basis materials per
+    detector channel, shape (2, n_cols): zero on the central channel, growing
+    as (gamma / gamma_max)^2 to (b1_edge, b2_edge) at the ends of the fan."""
+    k = np.arange(geom.n_cols)
+    gam = (k - 0.5 * (geom.n_cols - 1) - geom.col_offset) * geom.dgamma
+    s = (gam / np.abs(gam).max()) ** 2
+    return np.stack([b1_edge * s, b2_edge * s])
+
+
+def expected_counts(geom, phantom, I0, threads=None, bt=None):
+    """Expected counts (2, n_rays) of the continuous phantom, float64; with a
+    bowtie bt (2, n_cols) each ray sees the spectra attenuated by the filter
+    path of its channel."""
     if isinstance(phantom, MaterialPhantom):
         mu_t = phantom.mu_table()
         lengths = phantom.path_lengths
@@ -157,6 +169,10 @@ def expected_counts(geom, phantom, I0, threads=None):
         A = np.zeros((Lm.shape[0], mu_k.shape[1]))
         for m in range(Lm.shape[1]):
             A += Lm[:, m:m + 1] * mu_k[m][None, :]   # line integral per energy
+        if bt is not None:
+            kk = np.arange(A.shape[0]) % geom.n_cols
+            bmu = basis_mu()[:, keep]
+            A += bt[0][kk][:, None] * bmu[0][None, :] + bt[1][kk][:, None] * bmu[1][None, :]
         np.negative(A, out=A)
         np.exp(A, out=A)
         a = views[0] * geom.n_rows * geom.n_cols
@@ -169,7 +185,7 @@ def expected_counts(geom, phantom, I0, threads=None):
     return out
 
 
-def make_inputs(name: str, seed=None, i0=None, with_data=True):
+def make_inputs(name: str, seed=None, i0=None, with_data=True, with_bowtie=False):
     geom = geometry_for(name)
     i0_d, seed_d, n_iter = WORKLOADS[name]
     seed = seed_d if seed is None else seed
@@ -185,8 +201,11 @@ def make_inputs(name: str, seed=None, i0=None, with_data=True):
     inp["t"] = 0.5 * min(geom.dx, geom.dy)
     inp["c0"] = cold_start(geom, I0)
     inp["Z"] = surrogate_Z(geom, mu, I0)
+    bt = bowtie(geom) if with_bowtie else None
+    if bt is not None:
+        inp["bt"] = bt
     if with_data:
-        gbar = expected_counts(geom, ph, I0)
+        gbar = expected_counts(geom, ph, I0, bt=bt)
         rng = np.random.default_rng(seed)
         inp["gbar"] = gbar
         inp["d"] = rng.poisson(gbar).astype(np.float32)
