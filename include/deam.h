@@ -113,6 +113,17 @@ typedef struct deam_plan deam_plan;
 int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* I0,
                      const double* mu, int32_t precision, deam_plan** out);
 int deam_plan_destroy(deam_plan* plan);
+/* Bowtie filter (the energy- and channel-dependent I0_j(y,E) of Eq. 8): bt
+ * host [2][n_cols] holds the filter's path length (mm) in each basis
+ * material for every detector channel, so that the rays of channel k see
+ * I0_j(E) exp(-mu_1(E) bt[0][k] - mu_2(E) bt[1][k]) (exact for a filter
+ * whose attenuation lies in the basis).  It enters every energy sum of the
+ * plan (poly-mean, iterations, adjoints) as a per-channel offset of the line
+ * integrals; line integrals and the metal trace are unchanged; the MAR
+ * initialisation then returns DEAM_ERR_UNSUPPORTED.  bt = NULL removes the
+ * filter.  Values must be finite and >= 0.  Synchronous: call it while no
+ * call on the plan is in flight. */
+int deam_plan_set_bowtie(deam_plan* plan, const double* bt);
 /* Number of rays R and voxels V of the plan (host outputs). */
 int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels);
 /* Bytes of device workspace needed by an operation (deam_op). */

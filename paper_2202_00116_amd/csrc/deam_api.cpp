@@ -402,6 +402,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.row = G.view + (size_t)g.n_views * 4;
   G.rays = precision == DEAM_PREC_MIXED ? p->d_rays : p->d_rays64;
   G.rays64 = (const deam::RayXY<double>*)p->d_rays64;
+  G.bowtie = nullptr;
   G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
   G.V = (int64_t)g.nx * g.ny * G.nz;
 
@@ -447,7 +448,36 @@ int deam_plan_destroy(deam_plan* plan) {
   (void)hipFree(plan->d_energy);
   if (plan->d_rays) (void)hipFree(plan->d_rays);
   (void)hipFree(plan->d_rays64);
+  if (plan->d_bowtie) (void)hipFree(plan->d_bowtie);
   delete plan;
+  return ok();
+}
+
+int deam_plan_set_bowtie(deam_plan* plan, const double* bt) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!bt) {
+    if (plan->d_bowtie) (void)hipFree(plan->d_bowtie);
+    plan->d_bowtie = nullptr;
+    plan->gd.bowtie = nullptr;
+    return ok();
+  }
+  const int n = plan->gd.n_cols;
+  for (int i = 0; i < 2 * n; ++i)
+    if (!(std::isfinite(bt[i]) && bt[i] >= 0.0))
+      return fail(DEAM_ERR_VALUE, "bowtie path lengths must be finite and non-negative");
+  const bool dbl = plan->precision == DEAM_PREC_FP64;
+  std::vector<double> b64(bt, bt + 2 * n);
+  std::vector<float> b32(dbl ? 0 : 2 * n);
+  for (int i = 0; i < (int)b32.size(); ++i) b32[i] = (float)bt[i];
+  const size_t bytes = (size_t)2 * n * (dbl ? sizeof(double) : sizeof(float));
+  if (!plan->d_bowtie && hipMalloc(&plan->d_bowtie, bytes) != hipSuccess) {
+    plan->d_bowtie = nullptr;
+    return fail(DEAM_ERR_HIP, "hipMalloc of the bowtie table failed");
+  }
+  const void* src = dbl ? (const void*)b64.data() : (const void*)b32.data();
+  if (hipMemcpy(plan->d_bowtie, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(DEAM_ERR_HIP, "hipMemcpy of the bowtie table failed");
+  plan->gd.bowtie = plan->d_bowtie;
   return ok();
 }
 
@@ -766,6 +796,8 @@ int deam_mar_init(const deam_plan* plan, const float* d, const deam_mar_params* 
   if (int rc = check_plan(plan)) return rc;
   if (!d || !prm || !c64 || !M || !mask) return fail(DEAM_ERR_NULL, "d, prm, c64, M or mask is NULL");
   if (int rc = check_fbp(plan)) return rc;
+  if (plan->gd.bowtie)
+    return fail(DEAM_ERR_UNSUPPORTED, "the MAR initialisation does not model a bowtie filter");
   const double vals[] = {prm->t, prm->water[0], prm->water[1], prm->air_frac, prm->bone_frac,
                          prm->metal_frac, prm->eps};
   for (double v : vals)

@@ -40,6 +40,7 @@ struct GeomDev {
   const double* row;            // [n_rows][4]: zeta_r/dz (grid units), 3D ray length L_r (mm), dz/zeta_r (0 if zeta_r = 0), 0
   const void* rays;             // RayXY<T> [n_views][n_cols] in the plan precision
   const RayXY<double>* rays64;  // FP64 copy (metal trace, FP64 plans)
+  const void* bowtie;           // [2][n_cols] filter path in the basis (plan precision) or NULL
   int64_t R, V;
 };
 
@@ -134,6 +135,7 @@ struct deam_plan {
   // pre-weights sid cos(gamma_k) in d_tables (NULL when not supported),
   // photons per ray of each spectrum, and the inverse of the spectrum-weighted
   // attenuation matrix Mt[j][i] = sum_E I0_j mu_i / sum_E I0_j
+  void* d_bowtie;                // bowtie offsets [2][n_cols] (plan precision) or NULL
   const double* d_fbp;
   double i0sum[2];
   double mu_eff[2][2];

@@ -605,6 +605,11 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
       if (Tout) Tout[ray] = (double)l1;
       mask_out[ray] = (double)l1 >= tthr ? 1 : 0;
     } else {
+      if (G.bowtie) {  // the filter's path in the basis, in front of the energy sums
+        const T* bt = (const T*)G.bowtie;
+        l1 += bt[k];
+        l2 += bt[G.n_cols + k];
+      }
       poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, term, wabs);
     }
   }
@@ -853,7 +858,14 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
     } else {
       double tj = 0.0;
       T wj[4] = {0, 0, 0, 0};
-      poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, tj, wj);
+      T o1 = 0, o2 = 0;
+      if (G.bowtie) {  // the filter's path in the basis, in front of the energy sums
+        const T* bt = (const T*)G.bowtie;
+        o1 = bt[k];
+        o2 = bt[G.n_cols + k];
+      }
+      poly_epilogue<T, MODE>(eb, nE, l1 + o1, l2 + o2, ray, G.R, d, mask, nullptr, out, nullptr,
+                             tj, wj);
       term += tj;
 #pragma unroll
       for (int c = 0; c < 4; ++c) wabs[c] = fmax(wabs[c], wj[c]);
@@ -870,12 +882,19 @@ __global__ __launch_bounds__(kFpBlock) void k_poly(
     int64_t R, const EBin<T>* __restrict__ eb, int nE, const T* __restrict__ l,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, const T* __restrict__ v,
     T* __restrict__ w, T* __restrict__ gout, double* __restrict__ partial,
-    uint32_t* __restrict__ wmax) {
+    uint32_t* __restrict__ wmax, int n_cols, const T* __restrict__ bt) {
   const int64_t ray = (int64_t)blockIdx.x * kFpBlock + threadIdx.x;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
-  if (ray < R)
-    poly_epilogue<T, MODE>(eb, nE, l[ray], l[R + ray], ray, R, d, mask, v, w, gout, term, wabs);
+  if (ray < R) {
+    T l1 = l[ray], l2 = l[R + ray];
+    if (bt) {  // bowtie: the filter's path in the basis, per channel
+      const int k = (int)(ray % n_cols);
+      l1 += bt[k];
+      l2 += bt[n_cols + k];
+    }
+    poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, R, d, mask, v, w, gout, term, wabs);
+  }
   const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
   block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, wmax);
 }
@@ -1905,16 +1924,20 @@ static void poly_dispatch(const deam_plan* p, const void* l, const float* d, con
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
   if (mode == PM_AM)
     hipLaunchKernelGGL((k_poly<T, PM_AM>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)p->gd.bowtie);
   else if (mode == PM_GRAD)
     hipLaunchKernelGGL((k_poly<T, PM_GRAD>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d,
-                       mask, (const T*)v, (T*)w, (T*)g, partial, wmax);
+                       mask, (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)p->gd.bowtie);
   else if (mode == PM_VJP)
     hipLaunchKernelGGL((k_poly<T, PM_VJP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)p->gd.bowtie);
   else
     hipLaunchKernelGGL((k_poly<T, PM_STEP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax);
+                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)p->gd.bowtie);
 }
 
 hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,

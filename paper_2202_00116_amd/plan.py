@@ -199,6 +199,17 @@ class Plan:
                                                 _stream()))
         return c64
 
+    def set_bowtie(self, bt):
+        """Bowtie filter: bt (2, n_cols) path lengths (mm) in the basis per
+        channel, or None to remove it."""
+        if bt is None:
+            L.check(self.lib.deam_plan_set_bowtie(self._p, None))
+            return
+        b = np.ascontiguousarray(bt, dtype=np.float64)
+        if b.shape != (2, self.geom.n_cols):
+            raise ValueError(f"bowtie must have shape (2, {self.geom.n_cols})")
+        L.check(self.lib.deam_plan_set_bowtie(self._p, b.ctypes.data_as(C.c_void_p)))
+
     def dilate_mask(self, mask, radius):
         """Trace dilated by `radius` channels (same view and row)."""
         self._check(mask, (self.R,), torch.uint8, "mask")

@@ -104,3 +104,73 @@ def test_dilate_mask_matches_oracle(orc, radius):
     ref = orc.dilate_mask(g, mask, radius)
     assert np.array_equal(out, ref)
     assert out.sum() >= mask.sum()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_poly_mean_with_bowtie_matches_oracle(orc, prec, tol):
+    from paper_2202_00116_amd.plan import Plan
+    from paper_2202_00116_amd import _lib as L
+    inp = make_inputs("helical_small", with_bowtie=True)
+    g = inp["geom"]
+    mask = orc.metal_trace(g, inp["metal"], inp["t"])[0]
+    plan = Plan(g, inp["I0"], inp["mu"], prec)
+    plan.set_bowtie(inp["bt"])
+    l = orc.forward(g, inp["c0"])
+    lt = torch.tensor(l, dtype=plan.dtype, device=DEV)
+    l_used = lt.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(103)
+    v4 = rng.standard_normal((4, g.n_rays))
+    for mode, om in ((L.W_AM, orc.W_AM), (L.W_GRAD, orc.W_GRAD), (L.W_STEP_VJP, orc.W_STEP_VJP)):
+        v = torch.tensor(v4, dtype=plan.dtype, device=DEV) if mode == L.W_STEP_VJP else None
+        w, gg, _ = plan.poly_mean(lt, torch.tensor(inp["d"], device=DEV), torch.tensor(mask, device=DEV),
+                                  mode, v, want_g=True)
+        vr = None if v is None else v.cpu().numpy().astype(np.float64)
+        rw, rg, _ = orc.poly_mean_bt(inp["I0"], inp["mu"], inp["bt"], l_used, inp["d"], mask, om, vr)
+        e = max(float(np.abs(w.cpu().numpy() - rw).max() / np.abs(rw).max()),
+                float(np.abs(gg.cpu().numpy() - rg).max() / np.abs(rg).max()))
+        print(f"{prec} mode {mode}: poly-mean with bowtie max rel {e:.3e}")
+        assert e <= tol
+
+
+@pytest.mark.parametrize("name,n", [("fan64", 10), ("helical_small", 4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_iterate_with_bowtie_matches_oracle(orc, name, n, prec, tol):
+    from paper_2202_00116_amd.plan import Plan
+    inp = make_inputs(name, with_bowtie=True)
+    g = inp["geom"]
+    mask = orc.metal_trace(g, inp["metal"], inp["t"])[0]
+    ref, href = orc.iterate_bt(g, inp["I0"], inp["mu"], inp["bt"], inp["d"], mask, inp["Z"],
+                               inp["c0"], n)
+    plan = Plan(g, inp["I0"], inp["mu"], prec)
+    plan.set_bowtie(inp["bt"])
+    d = torch.tensor(inp["d"], device=DEV)
+    c = torch.tensor(inp["c0"], device=DEV)
+    h = torch.zeros(n, dtype=torch.float64, device=DEV)
+    plan.iterate(c, d, torch.tensor(mask, device=DEV), inp["Z"], n, h)
+    e = rel(c.cpu().numpy(), ref)
+    eh = float(np.abs(h.cpu().numpy() - href).max() / abs(href[0]))
+    print(f"{name} {prec} bowtie, {n} it.: image rel {e:.3e}, objective rel {eh:.3e}")
+    assert e <= tol and eh <= tol
+    # removing the filter gives the unfiltered iteration back exactly
+    plan.set_bowtie(None)
+    a = torch.tensor(inp["c0"], device=DEV)
+    b = a.clone()
+    plan.iterate(a, d, None, inp["Z"], 2)
+    Plan(g, inp["I0"], inp["mu"], prec).iterate(b, d, None, inp["Z"], 2)
+    assert torch.equal(a, b)
+
+
+def test_bowtie_rejects_bad_values_and_mar():
+    from paper_2202_00116_amd._lib import DeamError
+    from paper_2202_00116_amd.plan import Plan
+    from workloads import mar_params
+    inp = make_inputs("fan64", with_data=False, with_bowtie=True)
+    plan = Plan(inp["geom"], inp["I0"], inp["mu"], "mixed")
+    bad = inp["bt"].copy()
+    bad[0, 3] = -1.0
+    with pytest.raises(DeamError, match="VALUE"):
+        plan.set_bowtie(bad)
+    plan.set_bowtie(inp["bt"])
+    with pytest.raises(DeamError, match="UNSUPPORTED"):
+        plan.mar_init(torch.ones((2, plan.R), dtype=torch.float32, device=DEV),
+                      mar_params(inp["geom"], inp["I0"]))
