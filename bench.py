@@ -211,6 +211,57 @@ def measure(workload, K, W, K64, dev, log):
                "pipeline": "line integrals, FBP, metal/prior images, metal trace, prior projection, "
                            "NMAR, FBP, Eq. 4 decomposition"}
 
+    # model variants on this workload: ordered subsets (time per epoch and the
+    # objective after 4 epochs against 4 iterations), two scans (each with its
+    # own plan and trace), and a bowtie filter
+    variants = None
+    if g.kind == 0:
+        from paper_2202_00116_amd.plan import iterate_dual
+        from workloads import bowtie
+        n_sub, n_ep = 8, 4
+        h_os = torch.zeros(n_ep + 1, dtype=torch.float64, device=dev)
+        h_it = torch.zeros(n_ep + 1, dtype=torch.float64, device=dev)
+        c_os, c_it = c0.clone(), c0.clone()
+        plan.iterate_os(c_os, d, mask, Z, n_sub, n_ep + 1, h_os)
+        plan.iterate(c_it, d, mask, Z, n_ep + 1, h_it)
+        c_os = c0.clone()
+        plan.iterate_os(c_os, d, mask, Z, n_sub, 1)
+        e0.record()
+        plan.iterate_os(c_os, d, mask, Z, n_sub, K)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ep = e0.elapsed_time(e1) / K
+        I0 = inp["I0"]
+        lo, hi = np.zeros_like(I0), np.zeros_like(I0)
+        lo[0], hi[1] = I0[0], I0[1]
+        plo, phi = Plan(g, lo, inp["mu"], "mixed"), Plan(g, hi, inp["mu"], "mixed")
+        cd = c0.clone()
+        iterate_dual(plo, phi, cd, d, mask, d, mask, Z, 1)
+        e0.record()
+        iterate_dual(plo, phi, cd, d, mask, d, mask, Z, K)
+        e1.record()
+        torch.cuda.synchronize()
+        t_dual = e0.elapsed_time(e1) / K
+        del plo, phi
+        plan.set_bowtie(bowtie(g))
+        cb = c0.clone()
+        plan.iterate(cb, d, mask, Z, 1)
+        e0.record()
+        plan.iterate(cb, d, mask, Z, K)
+        e1.record()
+        torch.cuda.synchronize()
+        t_bt = e0.elapsed_time(e1) / K
+        plan.set_bowtie(None)
+        ho, hi_ = h_os.cpu().numpy(), h_it.cpu().numpy()
+        log(f"variants: OS-{n_sub} epoch {t_ep:.3f} ms, two scans {t_dual:.3f} ms/it, "
+            f"bowtie {t_bt:.3f} ms/it")
+        variants = {"ordered_subsets": {"n_sub": n_sub, "ms_per_epoch": t_ep,
+                                        "objective_after_4": float(ho[n_ep]),
+                                        "objective_after_4_iterations_plain": float(hi_[n_ep]),
+                                        "objective_start": float(ho[0])},
+                    "two_scans_ms_per_iteration": t_dual,
+                    "bowtie_ms_per_iteration": t_bt}
+
     # roofline of the dominant kernel, and of the whole iteration
     S = segment_count(g)
     nE = int((inp["I0"].sum(axis=0) > 0).sum())
@@ -234,7 +285,7 @@ def measure(workload, K, W, K64, dev, log):
                 fp64={"iterations_per_s": 1.0 / t_step64, "ms_per_step": t_step64 * 1e3,
                       "steps": K64},
                 speedup=t_step64 / t_step, roofline=roofline, iteration=iteration,
-                penalized=penalized, mar_init=mar)
+                penalized=penalized, mar_init=mar, variants=variants)
 
 
 def measure_unrolled(dev, log, batch=8, n_iter=10, reps=3):
@@ -356,6 +407,7 @@ def main():
         "iteration_roofline": m["iteration"],
         "penalized": m["penalized"],
         "mar_init": m["mar_init"],
+        "variants": m["variants"],
         "cpu_baseline": None,
     }
 
