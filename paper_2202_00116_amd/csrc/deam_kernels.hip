@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 namespace deam {
 namespace {
@@ -1061,7 +1062,7 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
 // afterwards through the general walk_row, so that the lanes of a wave stay
 // on the common path.
 template <typename T, bool Z3, int NCH, bool NONNEG>
-__global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
+__global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
                                                  double hmax, T* __restrict__ b) {
   // Packed accumulation (float plans, the 4 non-negative AM channels): the
@@ -1197,22 +1198,41 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
       const int sb8 = 8 * sbs;
       // byte offset of lateral index 0 in the current plane row and slice
       int row8 = 8 * (q0 * sa - lbb * sbs);
-      int C = 0;
+      int C = 0, cs = 0;
       if constexpr (Z3) {
         C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), tz0, tz1 - 1);
         row8 += 8 * (C - tz0) * TXY;
+        cs = ry.mw > (T)0 ? 1 : -1;
       }
+      // 3D: the step that holds the next crossing of a slice plane inside the
+      // tile (the chord is clipped to the tile's slices, so a tile face ends
+      // it): the plane w = wb is met at a = (wb - w0)/mw, and step q, which
+      // ends on plane la + q + 1, holds it when it lies in (start, end].
+      // Predicted once per crossing, not tested at every step; at least
+      // `lo`, the step being walked (a crossing is never skipped).
+      auto next_cross = [&](int lo) -> int {
+        const int wb = cs > 0 ? C + 1 : C;
+        if (ry.mw == (T)0 || wb <= tz0 || wb >= tz1) return 0x7fffffff;
+        const T qf = ceil(fabs((T)wb - ry.w0) * ry.imw) - (T)(la + 1);   // (wb - w0)/mw
+        return max((int)fmin(qf, (T)1e9), lo);
+      };
+      int qc = 0x7fffffff;
+      if constexpr (Z3) qc = next_cross(q0);
       uint32_t rest = 0;   // 3D: steps left to the general walk
-      // 3D: does the step ending at tn stay in the current slice?  If not,
-      // record it for the general walk and move to the new slice.
-      auto flat_step = [&](int q, T tn) {
+      // 3D: a step that crosses a slice plane is recorded for the general
+      // walk, and the walk moves on in the new slice.
+      auto cross = [&](int q) {
+        rest |= 1u << q;
+        do {
+          C += cs;
+          row8 += 8 * cs * TXY;
+          qc = next_cross(q);
+        } while (qc == q);
+      };
+      auto flat_step = [&](int q, T) {
         if constexpr (Z3) {
-          const int D = ifloor(fma(tn, ry.mw, ry.w0));
-          if (D != C) {
-            rest |= 1u << q;
-            const int C1 = clampi(D, tz0, tz1 - 1);
-            row8 += 8 * (C1 - C) * TXY;
-            C = C1;
+          if (q == qc) {
+            cross(q);
             return false;
           }
         }
@@ -1237,12 +1257,13 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
         tp = tn;
         bp = bn;
       };
-      // a full step [fa, fa + 1]
-      auto fstep = [&](int q) {
+      // a full step [fa, fa + 1] inside one slice (DEP), or one that crosses
+      // a slice plane and only advances the in-plane state (!DEP)
+      auto fstep = [&](auto dep) {
         fa += (T)1;
         const T bn = fma(fa, ry.mb, ry.b0);
         const int B = clampi(ifloor(bn), lbb, hb - 1);
-        if (flat_step(q, fa)) {
+        if constexpr (decltype(dep)::value) {
           const T dA = (B == A) ? (T)1 : clamp0(((T)max(A, B) - bp) * ry.imb, (T)1);
           QT qa[NCH];
           quant(dA, qa);
@@ -1259,9 +1280,20 @@ __global__ __launch_bounds__(bp_block<Z3>()) void k_bp(GeomDev G, Tiling TL, con
       };
       if (q0 < q1) {
         gstep(q0);
-        for (int q = q0 + 1; q < q1 - 1; ++q) fstep(q);
+        const int ql = q1 - 1;     // the last step (partial) is gstep's
+        int q = q0 + 1;
+        while (q < ql) {
+          // full steps up to the next slice crossing, then the crossing step
+          const int qe = min(qc, ql);
+          for (; q < qe; ++q) fstep(std::true_type{});
+          if (q < ql) {
+            cross(q);
+            fstep(std::false_type{});
+            ++q;
+          }
+        }
         tp = fa;   // the last step starts on a plane
-        if (q1 - 1 > q0) gstep(q1 - 1);
+        if (ql > q0) gstep(ql);
       }
       if constexpr (Z3) {
         const T iLa = (T)1 / ry.La;
