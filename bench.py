@@ -100,9 +100,11 @@ def iteration_model(g, S, nE):
     return ops, byt
 
 
-def measure(workload, K, W, K64, dev, log):
+def measure(workload, K, W, K64, dev, log, extras=True):
     """Mixed-precision step time, per-kernel times, the all-FP64 step time and
-    the roofline figures of one workload (inputs resident in HBM)."""
+    the roofline figures of one workload (inputs resident in HBM); with
+    extras, also the penalised iteration, the MAR initialisation and the model
+    variants (which launch the same kernels at other sizes)."""
     import torch
     from workloads import make_inputs, PENALTY
     from paper_2202_00116_amd.plan import Plan
@@ -160,34 +162,36 @@ def measure(workload, K, W, K64, dev, log):
 
     # penalised iteration (Eqs. 6-7) with the workload's (lambda, delta): whole
     # step, and the penalised update kernel alone on realistic backprojections
-    lam, delta = PENALTY[workload]
-    cpn = c0.clone()
-    plan.iterate_penalized(cpn, d, mask, Z, lam, delta, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.iterate_penalized(cpn, d, mask, Z, lam, delta, K)
-    torch.cuda.synchronize()
-    t_pen = (time.perf_counter() - t0) / K
-    wb, _, _ = plan.poly_mean(plan.forward(cpn.to(plan.dtype)), d, mask)
-    bb = plan.backproject(wb)
-    del wb
-    plan.update_penalized(cpn, bb, Z, lam, delta)
-    e0.record()
-    for _ in range(K):
+    penalized = None
+    if extras:
+        lam, delta = PENALTY[workload]
+        cpn = c0.clone()
+        plan.iterate_penalized(cpn, d, mask, Z, lam, delta, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.iterate_penalized(cpn, d, mask, Z, lam, delta, K)
+        torch.cuda.synchronize()
+        t_pen = (time.perf_counter() - t0) / K
+        wb, _, _ = plan.poly_mean(plan.forward(cpn.to(plan.dtype)), d, mask)
+        bb = plan.backproject(wb)
+        del wb
         plan.update_penalized(cpn, bb, Z, lam, delta)
-    e1.record()
-    torch.cuda.synchronize()
-    t_upd_pen = e0.elapsed_time(e1) / K
-    del bb
-    log(f"penalized: {t_pen * 1e3:.3f} ms/step, update kernel {t_upd_pen:.3f} ms")
-    penalized = {"lambda": lam, "delta": delta, "ms_per_step": t_pen * 1e3,
-                 "iterations_per_s": 1.0 / t_pen, "steps": K, "update_pen_ms": t_upd_pen,
-                 "update_ms": t_upd}
+        e0.record()
+        for _ in range(K):
+            plan.update_penalized(cpn, bb, Z, lam, delta)
+        e1.record()
+        torch.cuda.synchronize()
+        t_upd_pen = e0.elapsed_time(e1) / K
+        del bb
+        log(f"penalized: {t_pen * 1e3:.3f} ms/step, update kernel {t_upd_pen:.3f} ms")
+        penalized = {"lambda": lam, "delta": delta, "ms_per_step": t_pen * 1e3,
+                     "iterations_per_s": 1.0 / t_pen, "steps": K, "update_pen_ms": t_upd_pen,
+                     "update_ms": t_upd}
 
     # MAR initialisation (2D fan-beam full scans): the whole pipeline and one
     # two-channel FBP, events on torch's current stream
     mar = None
-    if g.kind == 0:
+    if extras and g.kind == 0:
         from workloads import mar_params
         prm = mar_params(g, inp["I0"])
         plan.mar_init(d, prm)
@@ -215,7 +219,7 @@ def measure(workload, K, W, K64, dev, log):
     # objective after 4 epochs against 4 iterations), two scans (each with its
     # own plan and trace), and a bowtie filter
     variants = None
-    if g.kind == 0:
+    if extras and g.kind == 0:
         from paper_2202_00116_amd.plan import iterate_dual
         from workloads import bowtie
         n_sub, n_ep = 8, 4
@@ -346,7 +350,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the helical and unrolled-reconstruction measurements")
+                    help="measure the main iteration only (skip the penalised, MAR and variant "
+                         "measurements and the helical and unrolled-reconstruction workloads)")
     ap.add_argument("--helical-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
@@ -376,7 +381,7 @@ def main():
     K, W = args.steps, args.warmup
     K64 = args.fp64_steps if args.fp64_steps is not None else max(2, K // 4)
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
-    m = measure(args.workload, K, W, K64, dev, log)
+    m = measure(args.workload, K, W, K64, dev, log, extras=not args.no_secondary)
     g, inp, t_step = m["inp"]["geom"], m["inp"], m["t_step"]
     plan, d, mask, c0, Z = m["plan"], m["d"], m["mask"], m["c0"], inp["Z"]
 
