@@ -2167,6 +2167,11 @@ hipError_t launch_fbp(const deam_plan* p, const void* sino, int n_ch, void* q, v
   const int64_t V = (int64_t)p->gd.nx * p->gd.ny;
   const dim3 bgrid((unsigned)((V + 255) / 256));
   const double scale = 2.0 * M_PI / p->gd.n_views;
+  // the weighted row and the kernel sit in LDS (up to 64 KiB at 4096 channels)
+  hipError_t e = hipFuncSetAttribute(
+      p->precision == DEAM_PREC_FP64 ? (const void*)k_fbp_filter<double> : (const void*)k_fbp_filter<float>,
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   if (p->precision == DEAM_PREC_FP64) {
     hipLaunchKernelGGL(k_fbp_filter<double>, fgrid, dim3(256), lds, st, n, p->gd.R,
                        (const double*)sino, p->d_fbp, p->gd.dgamma, (double*)q);

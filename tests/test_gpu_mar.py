@@ -145,3 +145,24 @@ def test_deam_from_mar_initialisation(mo, prec, tol):
     print(f"fan128 {prec}: DEAM from the MAR image, 20 it.: image rel {e:.3e}, objective rel {eh:.3e}")
     assert e <= tol and eh <= tol
     assert np.all(np.diff(href) < 0)
+
+
+def test_fbp_at_the_channel_limit(mo):
+    """4096 channels: the filter's row and kernel fill 64 KiB of LDS; one
+    more channel is refused."""
+    from paper_2202_00116_amd._lib import DeamError
+    I0, mu = _spectra()
+    g = Gw.fan2d(32, 1.0, 6, 4096)
+    plan = _plan(g, I0, mu, "fp64")
+    rng = np.random.default_rng(104)
+    p = torch.tensor(rng.uniform(0, 2, (1, g.n_rays)), device=DEV)
+    ref = mo.fbp(g, p.cpu().numpy())
+    out = plan.fbp(p).cpu().numpy()
+    # each filtered value sums ~2048 FP64 terms of both signs in another order
+    # than the oracle: n_cols * eps (~5e-13) times the cancellation of a noise
+    # sinogram
+    assert _relmax(out, ref) <= 1e-11
+    g2 = Gw.fan2d(32, 1.0, 6, 4097)
+    plan2 = _plan(g2, I0, mu, "mixed")
+    with pytest.raises(DeamError, match="UNSUPPORTED"):
+        plan2.fbp(torch.zeros((1, plan2.R), dtype=torch.float32, device=DEV))
