@@ -68,8 +68,27 @@ __device__ __forceinline__ float min_fin(float x, float hi) {
   return __builtin_amdgcn_fmed3f(x, hi, -3.0e38f);
 }
 __device__ __forceinline__ double min_fin(double x, double hi) { return fmin(x, hi); }
-__device__ __forceinline__ float dexp(float x) { return expf(x); }
-__device__ __forceinline__ double dexp(double x) { return exp(x); }
+// Attenuation exp(-(mu1 l1 + mu2 l2)) of one energy bin, given the ray's
+// line integrals as prepared by bin_args: FP32 plans scale them by log2(e)
+// once per ray and use the hardware 2^x (one instruction per bin; the
+// argument is rounded once, as it is for exp); FP64 plans use exp.
+template <typename T>
+__device__ __forceinline__ void bin_args(T l1, T l2, T& k1, T& k2) {
+  if constexpr (sizeof(T) == 4) {
+    k1 = l1 * 1.44269504088896340736f;
+    k2 = l2 * 1.44269504088896340736f;
+  } else {
+    k1 = l1;
+    k2 = l2;
+  }
+}
+template <typename T>
+__device__ __forceinline__ T bin_att(T mu1, T mu2, T k1, T k2) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_exp2f(-fma(mu1, k1, mu2 * k2));
+  else
+    return exp(-fma(mu1, k1, mu2 * k2));
+}
 
 template <bool PK> struct QType { using type = unsigned long long; };
 template <> struct QType<true> { using type = uint32_t; };
@@ -367,12 +386,14 @@ template <typename T>
 __device__ void energy_sums(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, T g[2],
                             T a[2][2]) {
   T S[6] = {0, 0, 0, 0, 0, 0}, C[6] = {0, 0, 0, 0, 0, 0};
+  T k1, k2;
+  bin_args(l1, l2, k1, k2);
   for (int e0 = 0; e0 < nE; e0 += 8) {  // nE is padded to a multiple of 8
     T p[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const EBin<T> B = eb[e0 + e];
-      const T ex = dexp(-fma(B.mu1, l1, B.mu2 * l2));
+      const T ex = bin_att(B.mu1, B.mu2, k1, k2);
       p[0] = fma(B.i0l, ex, p[0]);
       p[1] = fma(B.i0h, ex, p[1]);
       p[2] = fma(B.m1l, ex, p[2]);
@@ -399,6 +420,8 @@ __device__ void energy_sums2(const EBin<T>* __restrict__ eb, int nE, T l1, T l2,
   T S[12], C[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) S[i] = C[i] = 0;
+  T k1, k2;
+  bin_args(l1, l2, k1, k2);
   for (int e0 = 0; e0 < nE; e0 += 8) {
     T p[12];
 #pragma unroll
@@ -406,7 +429,7 @@ __device__ void energy_sums2(const EBin<T>* __restrict__ eb, int nE, T l1, T l2,
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const EBin<T> B = eb[e0 + e];
-      const T ex = dexp(-fma(B.mu1, l1, B.mu2 * l2));
+      const T ex = bin_att(B.mu1, B.mu2, k1, k2);
       p[0] = fma(B.i0l, ex, p[0]);
       p[1] = fma(B.i0h, ex, p[1]);
       p[2] = fma(B.m1l, ex, p[2]);
