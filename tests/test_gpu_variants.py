@@ -174,3 +174,36 @@ def test_bowtie_rejects_bad_values_and_mar():
     with pytest.raises(DeamError, match="UNSUPPORTED"):
         plan.mar_init(torch.ones((2, plan.R), dtype=torch.float32, device=DEV),
                       mar_params(inp["geom"], inp["I0"]))
+
+
+def test_variants_full_fan512(orc):
+    """The 512 x 512 benchmark workload, one iteration each: two scans (the
+    high-energy scan rotated by half a view and shifted by a quarter channel)
+    and a bowtie filter, mixed precision, against the oracle."""
+    from paper_2202_00116_amd.plan import Plan, iterate_dual
+    inp, gl, gh, dh, ml, mh = _two_scans(orc, "fan512")
+    ref, _ = orc.iterate_dual((gl, gh), inp["I0"], inp["mu"], (inp["d"][0], dh), (ml, mh), inp["Z"],
+                              inp["c0"], 1)
+    plo = Plan(gl, _one_spectrum(inp["I0"], 0), inp["mu"], "mixed")
+    phi = Plan(gh, _one_spectrum(inp["I0"], 1), inp["mu"], "mixed")
+    d_lo = torch.zeros((2, plo.R), dtype=torch.float32, device=DEV)
+    d_lo[0] = torch.tensor(inp["d"][0], device=DEV)
+    d_hi = torch.zeros((2, phi.R), dtype=torch.float32, device=DEV)
+    d_hi[1] = torch.tensor(dh, dtype=torch.float32, device=DEV)
+    c = torch.tensor(inp["c0"], device=DEV)
+    iterate_dual(plo, phi, c, d_lo, torch.tensor(ml, device=DEV), d_hi, torch.tensor(mh, device=DEV),
+                 inp["Z"], 1)
+    e = rel(c.cpu().numpy(), ref)
+    print(f"fan512 two scans, 1 it.: image rel {e:.3e}")
+    assert e <= 1e-5
+    inb = make_inputs("fan512", with_bowtie=True)
+    g = inb["geom"]
+    mask = orc.metal_trace(g, inb["metal"], inb["t"])[0]
+    ref, _ = orc.iterate_bt(g, inb["I0"], inb["mu"], inb["bt"], inb["d"], mask, inb["Z"], inb["c0"], 1)
+    plan = Plan(g, inb["I0"], inb["mu"], "mixed")
+    plan.set_bowtie(inb["bt"])
+    c = torch.tensor(inb["c0"], device=DEV)
+    plan.iterate(c, torch.tensor(inb["d"], device=DEV), torch.tensor(mask, device=DEV), inb["Z"], 1)
+    e = rel(c.cpu().numpy(), ref)
+    print(f"fan512 bowtie, 1 it.: image rel {e:.3e}")
+    assert e <= 1e-5
