@@ -246,6 +246,18 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
                     const double* Z, int32_t n_sub, int32_t n_iter, double* obj_hist, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* Bit-packed trace (1 bit per ray instead of 1 byte: 7.5 MB instead of 60 MB
+ * for 60 M rays): bit b of bits[i] is mask[32 i + b] != 0.
+ *   mask [R] uint8;  bits [ceil(R / 32)] uint32 output. */
+int deam_pack_mask(const deam_plan* plan, const uint8_t* mask, uint32_t* bits, void* stream);
+
+/* deam_iterate with the trace given bit-packed (deam_pack_mask's layout);
+ * same results as deam_iterate with the byte mask, bit for bit.
+ * Workspace: deam_workspace_size(DEAM_OP_ITERATE). */
+int deam_iterate_packed(const deam_plan* plan, double* c64, const float* d,
+                        const uint32_t* mask_bits, const double* Z, int32_t n_iter,
+                        double* obj_hist, void* ws, size_t ws_bytes, void* stream);
+
 /* Vector-Jacobian product of one DEAM iteration (the differentiable form of
  * deam_iterate, for losses on the reconstructed image): with
  * Phi(c) = c - ln(b~(c) / b^(c)) / Z (the update of deam_update, c unchanged

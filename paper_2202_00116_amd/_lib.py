@@ -26,7 +26,8 @@ EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_wor
            "deam_update", "deam_iterate", "deam_iterate_timed", "deam_iterate_vjp",
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
            "deam_fbp", "deam_nmar", "deam_mar_init", "deam_iterate_os", "deam_dual_workspace_size",
-           "deam_iterate_dual", "deam_dilate_mask", "deam_plan_set_bowtie", "deam_last_error")
+           "deam_iterate_dual", "deam_dilate_mask", "deam_plan_set_bowtie", "deam_pack_mask",
+           "deam_iterate_packed", "deam_last_error")
 
 
 class DeamGeometry(C.Structure):
@@ -86,6 +87,8 @@ def load():
         "deam_dual_workspace_size": [vp, vp, C.POINTER(sz)],
         "deam_dilate_mask": [vp, vp, i32, vp, vp],
         "deam_plan_set_bowtie": [vp, vp],
+        "deam_pack_mask": [vp, vp, vp, vp],
+        "deam_iterate_packed": [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
         "deam_iterate_dual": [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
     }
     for name, args in sig.items():

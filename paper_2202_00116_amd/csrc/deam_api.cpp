@@ -403,6 +403,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.rays = precision == DEAM_PREC_MIXED ? p->d_rays : p->d_rays64;
   G.rays64 = (const deam::RayXY<double>*)p->d_rays64;
   G.bowtie = nullptr;
+  G.mbits = nullptr;
   G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
   G.V = (int64_t)g.nx * g.ny * G.nz;
 
@@ -999,6 +1000,23 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   HIP_TRY(deam::launch_backproject(plan, w + L.lam, 2, false, wmax, w + L.bl, st));
   HIP_TRY(deam::launch_add_g(plan, G, w + L.bl, out, st));
   return ok();
+}
+
+int deam_pack_mask(const deam_plan* plan, const uint8_t* mask, uint32_t* bits, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!mask || !bits) return fail(DEAM_ERR_NULL, "mask or bits is NULL");
+  HIP_TRY(deam::launch_pack_mask(plan, mask, bits, (hipStream_t)stream));
+  return ok();
+}
+
+int deam_iterate_packed(const deam_plan* plan, double* c64, const float* d,
+                        const uint32_t* mask_bits, const double* Z, int32_t n_iter,
+                        double* obj_hist, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!mask_bits) return fail(DEAM_ERR_NULL, "mask_bits is NULL");
+  deam_plan q = *plan;   // the same plan reading the bit-packed trace
+  q.gd.mbits = mask_bits;
+  return iterate_impl(&q, c64, d, nullptr, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
 }
 
 int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,

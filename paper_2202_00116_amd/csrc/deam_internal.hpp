@@ -41,6 +41,7 @@ struct GeomDev {
   const void* rays;             // RayXY<T> [n_views][n_cols] in the plan precision
   const RayXY<double>* rays64;  // FP64 copy (metal trace, FP64 plans)
   const void* bowtie;           // [2][n_cols] filter path in the basis (plan precision) or NULL
+  const uint32_t* mbits;        // bit-packed trace read instead of the byte mask, or NULL
   int64_t R, V;
 };
 
@@ -195,6 +196,8 @@ hipError_t launch_mar_classes(const deam_plan* p, const void* mu0, const double 
                               hipStream_t st);
 hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, uint8_t* out,
                          hipStream_t st);
+hipError_t launch_pack_mask(const deam_plan* p, const uint8_t* mask, uint32_t* bits,
+                            hipStream_t st);
 hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hipStream_t st);
 
 WsLayout workspace_layout(const deam_plan* p, int op);

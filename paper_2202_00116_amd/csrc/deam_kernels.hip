@@ -478,14 +478,17 @@ template <typename T, int MODE>
 __device__ void poly_epilogue(const EBin<T>* __restrict__ eb, int nE, T l1, T l2, int64_t ray,
                               int64_t R, const float* __restrict__ d,
                               const uint8_t* __restrict__ mask, const T* __restrict__ v,
-                              T* __restrict__ w, T* __restrict__ gout, double& term, T wabs[4]) {
+                              T* __restrict__ w, T* __restrict__ gout, double& term, T wabs[4],
+                              const uint32_t* __restrict__ mbits = nullptr) {
   T g[2], a[2][2];
   [[maybe_unused]] T m[2][3];
   if constexpr (MODE == PM_STEP)
     energy_sums2<T>(eb, nE, l1, l2, g, a, m);
   else
     energy_sums<T>(eb, nE, l1, l2, g, a);
-  const bool metal = mask != nullptr && mask[ray] != 0;
+  // the trace: one byte per ray, or (mbits) one bit per ray, bit (ray % 32) of word ray / 32
+  const bool metal = mbits ? ((mbits[ray >> 5] >> (ray & 31)) & 1u) != 0
+                           : (mask != nullptr && mask[ray] != 0);
   if (gout) {
     gout[ray] = g[0];
     gout[R + ray] = g[1];
@@ -634,7 +637,8 @@ __global__ __launch_bounds__(kFpBlock) void k_fp(
         l1 += bt[k];
         l2 += bt[G.n_cols + k];
       }
-      poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, term, wabs);
+      poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, G.R, d, mask, nullptr, out, nullptr, term, wabs,
+                             G.mbits);
     }
   }
   if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
@@ -889,7 +893,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
         o2 = bt[G.n_cols + k];
       }
       poly_epilogue<T, MODE>(eb, nE, l1 + o1, l2 + o2, ray, G.R, d, mask, nullptr, out, nullptr,
-                             tj, wj);
+                             tj, wj, G.mbits);
       term += tj;
 #pragma unroll
       for (int c = 0; c < 4; ++c) wabs[c] = fmax(wabs[c], wj[c]);
@@ -1878,6 +1882,20 @@ __global__ __launch_bounds__(256) void k_dilate(int64_t R, int n_cols, int radiu
   out[y] = m ? 1 : 0;
 }
 
+// Bit-packed trace: bit b of word i is mask[32 i + b] != 0 (one wave per
+// 64 words; rays past R give 0 bits).
+__global__ __launch_bounds__(256) void k_pack_mask(int64_t R, const uint8_t* __restrict__ mask,
+                                                   uint32_t* __restrict__ bits) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // word
+  const int64_t nw = (R + 31) / 32;
+  if (i >= nw) return;
+  uint32_t wv = 0;
+  const int64_t y0 = i * 32;
+  for (int b = 0; b < 32; ++b)
+    if (y0 + b < R && mask[y0 + b]) wv |= 1u << b;
+  bits[i] = wv;
+}
+
 inline dim3 image_grid(const deam_plan* p) {
   return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
 }
@@ -2256,7 +2274,16 @@ hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, ui
   return hipGetLastError();
 }
 
+hipError_t launch_pack_mask(const deam_plan* p, const uint8_t* mask, uint32_t* bits,
+                            hipStream_t st) {
+  const int64_t nw = (p->gd.R + 31) / 32;
+  hipLaunchKernelGGL(k_pack_mask, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, p->gd.R,
+                     mask, bits);
+  return hipGetLastError();
+}
+
 }  // namespace deam
+
 
 
 

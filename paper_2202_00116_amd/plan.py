@@ -199,6 +199,26 @@ class Plan:
                                                 _stream()))
         return c64
 
+    def pack_mask(self, mask):
+        """Bit-packed trace: int32 tensor of ceil(R / 32) words."""
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        bits = torch.empty((self.R + 31) // 32, dtype=torch.int32, device=self.device)
+        L.check(self.lib.deam_pack_mask(self._p, _ptr(mask), _ptr(bits), _stream()))
+        return bits
+
+    def iterate_packed(self, c64, d, bits, Z, n_iter, obj_hist=None):
+        """iterate() with the bit-packed trace of pack_mask()."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(bits, ((self.R + 31) // 32,), torch.int32, "bits")
+        self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        ws, n = self.workspace(L.OP_ITERATE)
+        L.check(self.lib.deam_iterate_packed(self._p, _ptr(c64), _ptr(d), _ptr(bits),
+                                             Zh.ctypes.data_as(C.c_void_p), int(n_iter),
+                                             _ptr(obj_hist), ws, n, _stream()))
+        return c64
+
     def set_bowtie(self, bt):
         """Bowtie filter: bt (2, n_cols) path lengths (mm) in the basis per
         channel, or None to remove it."""

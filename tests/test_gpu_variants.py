@@ -207,3 +207,36 @@ def test_variants_full_fan512(orc):
     e = rel(c.cpu().numpy(), ref)
     print(f"fan512 bowtie, 1 it.: image rel {e:.3e}")
     assert e <= 1e-5
+
+
+def test_pack_mask_layout():
+    """Bit b of word i is ray 32 i + b, on a ray count that is not a multiple of 32."""
+    from paper_2202_00116_amd.plan import Plan
+    import workloads.geometry as Gw
+    inp = make_inputs("fan64", with_data=False)
+    g = Gw.fan2d(16, 1.0, 7, 45)
+    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
+    assert plan.R % 32 != 0
+    rng = np.random.default_rng(105)
+    m = (rng.uniform(size=plan.R) < 0.3).astype(np.uint8)
+    bits = plan.pack_mask(torch.tensor(m, device=DEV)).cpu().numpy().view(np.uint32)
+    ref = np.packbits(np.concatenate([m, np.zeros(len(bits) * 32 - plan.R, np.uint8)]),
+                      bitorder="little").view(np.uint32)
+    assert np.array_equal(bits, ref)
+
+
+@pytest.mark.parametrize("name", ["fan64", "helical_small"])
+def test_iterate_packed_is_iterate(orc, name):
+    from paper_2202_00116_amd.plan import Plan
+    inp = make_inputs(name)
+    g = inp["geom"]
+    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
+    mask = torch.tensor(orc.metal_trace(g, inp["metal"], inp["t"])[0], device=DEV)
+    d = torch.tensor(inp["d"], device=DEV)
+    a = torch.tensor(inp["c0"], device=DEV)
+    b = a.clone()
+    ha = torch.zeros(4, dtype=torch.float64, device=DEV)
+    hb = torch.zeros(4, dtype=torch.float64, device=DEV)
+    plan.iterate(a, d, mask, inp["Z"], 4, ha)
+    plan.iterate_packed(b, d, plan.pack_mask(mask), inp["Z"], 4, hb)
+    assert torch.equal(a, b) and torch.equal(ha, hb)
