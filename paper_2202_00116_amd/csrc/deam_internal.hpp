@@ -132,11 +132,11 @@ struct deam_plan {
   double hmax;                   // upper bound of one h(x,y): the voxel diagonal
   int64_t fp_blocks;             // blocks of the fused projector kernel (its FP64 partials)
   int64_t ray_blocks;            // blocks of one-thread-per-ray kernels
+  void* d_bowtie;                // bowtie offsets [2][n_cols] (plan precision) or NULL
   // MAR initialisation (2D fan-beam full scans): ramp kernel g(0..n-1) and
   // pre-weights sid cos(gamma_k) in d_tables (NULL when not supported),
   // photons per ray of each spectrum, and the inverse of the spectrum-weighted
   // attenuation matrix Mt[j][i] = sum_E I0_j mu_i / sum_E I0_j
-  void* d_bowtie;                // bowtie offsets [2][n_cols] (plan precision) or NULL
   const double* d_fbp;
   double i0sum[2];
   double mu_eff[2][2];
