@@ -166,3 +166,31 @@ def test_fbp_at_the_channel_limit(mo):
     plan2 = _plan(g2, I0, mu, "mixed")
     with pytest.raises(DeamError, match="UNSUPPORTED"):
         plan2.fbp(torch.zeros((1, plan2.R), dtype=torch.float32, device=DEV))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mar_init_without_metal(mo, prec):
+    """A scan with no metal and some photon-starved rays: the metal image and
+    the trace are empty, NMAR leaves the data alone, and c is Eq. 4 of the
+    first FBP; against the oracle."""
+    import dataclasses
+    from workloads.configs import expected_counts, phantom_for
+    from workloads.phantoms import MaterialPhantom, METALS
+    inp = make_inputs("fan128", with_data=False)
+    g = inp["geom"]
+    ph = phantom_for("fan128")
+    ph = MaterialPhantom([dataclasses.replace(o, material=o.parent) if o.material in METALS else o
+                          for o in ph.objects])
+    d = np.random.default_rng(106).poisson(expected_counts(g, ph, inp["I0"])).astype(np.float32)
+    # a few starved rays, counted as one photon: sparse enough that their
+    # streaks stay below the metal threshold (3.9 x water at the peak)
+    d[:, ::4999] = 0.0
+    prm = mar_params(g, inp["I0"])
+    ref = mo.mar_init(g, inp["I0"], inp["mu"], d, prm)
+    assert ref["M"].sum() == 0 and ref["mask"].sum() == 0
+    plan = _plan(g, inp["I0"], inp["mu"], prec)
+    c, M, mask = plan.mar_init(torch.tensor(d, device=DEV), prm)
+    assert int(M.sum()) == 0 and int(mask.sum()) == 0
+    e = float(np.linalg.norm(c.cpu().numpy() - ref["c"]) / np.linalg.norm(ref["c"]))
+    assert e <= (5e-4 if prec == "mixed" else 1e-10), e
+    assert np.allclose(mo.decompose(ref["mu0"], inp["I0"], inp["mu"]), ref["c"], rtol=1e-12, atol=1e-14)
