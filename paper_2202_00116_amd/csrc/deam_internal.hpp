@@ -60,22 +60,22 @@ struct Tiling {
   int ntx, nty, ntz;
 };
 
-// Tile shape of the backprojector for NCH channels: 16 x 16 pixels in 2D;
+// Tile shape of the backprojector for NCH channels: 32 x 32 pixels in 2D;
 // in 3D flat 32 x 32 x tz slabs (rays are close to the slice planes, so a
 // wide, thin slab gives long in-tile paths).  PK: two channels share one
 // 64-bit LDS word (non-negative weights, see the kernel).  At most 80 KiB of
 // LDS, so two tiles share a CU.
-// Threads per tile: 256 in 2D, so that all tiles of a 512 x 512 image are
-// resident at once (four per CU); 512 in 3D.
+// Threads per tile: 1024 in 2D (one tile of a 512 x 512 image per CU, 16
+// waves); 512 in 3D (two tiles per CU).
 template <bool Z3>
-constexpr int bp_block() { return Z3 ? 512 : 256; }
+constexpr int bp_block() { return Z3 ? 512 : 1024; }
 
 template <bool Z3, int NCH, bool PK>
 struct BpTile {
   static constexpr int block = bp_block<Z3>();
   static constexpr int wpv = PK ? NCH / 2 : NCH;   // 64-bit LDS words per voxel
-  static constexpr int tx = Z3 ? 32 : 16;
-  static constexpr int ty = Z3 ? 32 : 16;
+  static constexpr int tx = 32;
+  static constexpr int ty = 32;
   static constexpr int tz = Z3 ? (PK ? 2 : 8 / NCH) : 1;
   static constexpr size_t lds_bytes = (size_t)(tx + 1) * ty * tz * wpv * 8;
   static_assert(lds_bytes <= 81920, "backprojection tile exceeds 80 KiB");
