@@ -96,7 +96,11 @@ inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
   const int64_t ng = (n_rows + rg - 1) / rg;
   return nvb * nkb * ng;
 }
-constexpr int kViewBatch = 64;
+// Views per backprojector batch: each batch ends in a barrier that waits for
+// the tile's slowest wave (in 2D a tile holds a whole CU), so a batch should
+// give every thread several items; the packed accumulation's resolution
+// shrinks in proportion to it
+constexpr int kViewBatch = 128;
 constexpr int kMaxFbpCols = 4096;   // FBP filter: one detector row of p and g in LDS (64 KiB)
 
 // Workspace pieces (byte offsets, 256-aligned).

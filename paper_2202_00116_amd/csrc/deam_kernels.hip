@@ -993,20 +993,20 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
   return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
 }
 
-// View set-up of a tile for one batch of kViewBatch views (all threads of
+// View set-up of a tile for one batch of VB views (all threads of
 // the block take part; three barriers).  For every view of the batch: the
 // channels [kl, kl + nk) whose rays can meet the tile, from the channel
 // coordinates of the tile's corners, and the detector rows [rl, rl + nr)
 // whose rays can meet its slices, from its z-range and its distance to the
 // source; s_off receives the exclusive prefix sum of the work items per view,
 // nk * ceil(nr / RG).
-template <int RG>
+template <int RG, int VB>
 __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0, double X1,
                                            double Y0, double Y1, double Z0, double Z1,
                                            float (*s_kap)[4], int* s_kl, int* s_nk, int* s_rl,
                                            int* s_nr, int* s_off) {
-  static_assert(kViewBatch % 64 == 0, "the prefix sum runs over whole waves of views");
-  for (int i = threadIdx.x; i < 4 * kViewBatch; i += blockDim.x) {
+  static_assert(VB % 64 == 0, "the prefix sum runs over whole waves of views");
+  for (int i = threadIdx.x; i < 4 * VB; i += blockDim.x) {
     const int j = i >> 2, cn = i & 3;
     const int v = G.voff + G.vsub * (vb0 + j);
     float kap = 0.f;
@@ -1021,7 +1021,7 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
   }
   __syncthreads();
   // channel and row ranges of each view
-  for (int j = threadIdx.x; j < kViewBatch; j += blockDim.x) {
+  for (int j = threadIdx.x; j < VB; j += blockDim.x) {
     const int v = G.voff + G.vsub * (vb0 + j);
     int kl = 0, nk = 0, rl = 0, nr = 0;
     if (vb0 + j < G.nvl) {
@@ -1059,7 +1059,7 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
     int carry = 0;
     if (lane == 0) s_off[0] = 0;
 #pragma unroll
-    for (int c = 0; c < kViewBatch; c += 64) {
+    for (int c = 0; c < VB; c += 64) {
       int run = s_nk[c + lane] * ((s_nr[c + lane] + RG - 1) / RG);
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
@@ -1107,9 +1107,10 @@ __global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(
   constexpr int NOWN = PK ? (NW + NT - 1) / NT : 1;
   static_assert(BT::tx <= 32 && BT::ty <= 32, "deferred steps live in a 32-bit mask");
   extern __shared__ unsigned long long acc[];
-  __shared__ float s_kap[kViewBatch][4];
-  __shared__ int s_kl[kViewBatch], s_nk[kViewBatch], s_rl[kViewBatch], s_nr[kViewBatch];
-  __shared__ int s_off[kViewBatch + 1];
+  constexpr int VB = kViewBatch;
+  __shared__ float s_kap[VB][4];
+  __shared__ int s_kl[VB], s_nk[VB], s_rl[VB], s_nr[VB];
+  __shared__ int s_off[VB + 1];
   const RayXY<T>* __restrict__ rays =
       (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
 
@@ -1129,9 +1130,9 @@ __global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
   for (int o = 0; o < 2 * NOWN; ++o) tot[o] = 0ull;
 
-  // h1 bounds max_x sum_y h(x,y) over all views; a batch of kViewBatch views
-  // contributes at most the fraction kViewBatch / n_views of it
-  const double hb = h1 * (double)min(kViewBatch, G.nvl) / (double)G.n_views;
+  // h1 bounds max_x sum_y h(x,y) over all views (n_views times a per-view
+  // bound); a batch of VB views contributes at most VB / n_views of it
+  const double hb = h1 * (double)min(VB, G.nvl) / (double)G.n_views;
   T scl[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -1152,14 +1153,14 @@ __global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(
   const double Z0 = G.z0 + tz0 * G.dz, Z1 = G.z0 + tz1 * G.dz;
   __syncthreads();
 
-  for (int vb0 = 0; vb0 < G.nvl; vb0 += kViewBatch) {
-    cull_views<1>(G, vb0, X0, X1, Y0, Y1, Z0, Z1, s_kap, s_kl, s_nk, s_rl, s_nr, s_off);
-    const int total = s_off[kViewBatch];
+  for (int vb0 = 0; vb0 < G.nvl; vb0 += VB) {
+    cull_views<1, VB>(G, vb0, X0, X1, Y0, Y1, Z0, Z1, s_kap, s_kl, s_nk, s_rl, s_nr, s_off);
+    const int total = s_off[VB];
     for (int it = threadIdx.x; it < total; it += NT) {
       // view of the item: the last j with s_off[j] <= it (binary search)
       int j = 0;
 #pragma unroll
-      for (int step = kViewBatch / 2; step > 0; step >>= 1)
+      for (int step = VB / 2; step > 0; step >>= 1)
         if (s_off[j + step] <= it) j += step;
       const int loc = it - s_off[j];
       const int nk = s_nk[j];
