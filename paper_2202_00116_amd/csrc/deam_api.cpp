@@ -266,6 +266,12 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     delete p;
     return fail(DEAM_ERR_HIP, "hipGetDevice failed");
   }
+  if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) !=
+          hipSuccess ||
+      p->n_cu < 1) {
+    delete p;
+    return fail(DEAM_ERR_HIP, "hipDeviceGetAttribute(multiprocessor count) failed");
+  }
 
   // geometry tables (FP64): per view [cos b, sin b, z_s, w_s], per row [zeta_r/dz, L_r, dz/zeta_r, 0]
   const double x0 = -0.5 * g.nx * g.dx, y0 = -0.5 * g.ny * g.dy;

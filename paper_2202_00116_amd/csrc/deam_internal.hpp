@@ -60,22 +60,24 @@ struct Tiling {
   int ntx, nty, ntz;
 };
 
-// Tile shape of the backprojector for NCH channels: 32 x 32 pixels in 2D;
-// in 3D flat 32 x 32 x tz slabs (rays are close to the slice planes, so a
-// wide, thin slab gives long in-tile paths).  PK: two channels share one
-// 64-bit LDS word (non-negative weights, see the kernel).  At most 80 KiB of
-// LDS, so two tiles share a CU.
-// Threads per tile: 1024 in 2D (one tile of a 512 x 512 image per CU, 16
-// waves); 512 in 3D (two tiles per CU).
-template <bool Z3>
-constexpr int bp_block() { return Z3 ? 512 : 1024; }
+// Tile shape of the backprojector for NCH channels: 32 x 32 pixels in 2D,
+// or 16 x 16 (SM) for images with fewer 32 x 32 tiles than compute units; in
+// 3D flat 32 x 32 x tz slabs (rays are close to the slice planes, so a wide,
+// thin slab gives long in-tile paths).  PK: two channels share one 64-bit LDS
+// word (non-negative weights, see the kernel).  At most 80 KiB of LDS, so
+// two tiles share a CU.
+// Threads per tile: 1024 in 2D (a whole CU, 16 waves), 256 for SM tiles (four
+// per CU); 512 in 3D (two tiles per CU).
+template <bool Z3, bool SM>
+constexpr int bp_block() { return Z3 ? 512 : (SM ? 256 : 1024); }
 
-template <bool Z3, int NCH, bool PK>
+template <bool Z3, int NCH, bool PK, bool SM>
 struct BpTile {
-  static constexpr int block = bp_block<Z3>();
+  static_assert(!(Z3 && SM), "small tiles are 2D only");
+  static constexpr int block = bp_block<Z3, SM>();
   static constexpr int wpv = PK ? NCH / 2 : NCH;   // 64-bit LDS words per voxel
-  static constexpr int tx = 32;
-  static constexpr int ty = 32;
+  static constexpr int tx = SM ? 16 : 32;
+  static constexpr int ty = SM ? 16 : 32;
   static constexpr int tz = Z3 ? (PK ? 2 : 8 / NCH) : 1;
   static constexpr size_t lds_bytes = (size_t)(tx + 1) * ty * tz * wpv * 8;
   static_assert(lds_bytes <= 81920, "backprojection tile exceeds 80 KiB");
@@ -136,6 +138,7 @@ struct deam_plan {
   double hmax;                   // upper bound of one h(x,y): the voxel diagonal
   int64_t fp_blocks;             // blocks of the fused projector kernel (its FP64 partials)
   int64_t ray_blocks;            // blocks of one-thread-per-ray kernels
+  int n_cu;                      // compute units of the plan's device
   void* d_bowtie;                // bowtie offsets [2][n_cols] (plan precision) or NULL
   // MAR initialisation (2D fan-beam full scans): ramp kernel g(0..n-1) and
   // pre-weights sid cos(gamma_k) in d_tables (NULL when not supported),

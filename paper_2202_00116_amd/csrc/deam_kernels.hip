@@ -1075,7 +1075,7 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
 }
 
 // One backprojector for both geometries.  A workgroup owns a tile of
-// BpTile<Z3, NCH> voxels in LDS and scatters every ray that meets it, view
+// BpTile<Z3, NCH, PK, SM> voxels in LDS and scatters every ray that meets it, view
 // batch by view batch; work items are (view, detector row, channel) with the
 // channel fastest, so neighbouring lanes walk neighbouring rays.
 //
@@ -1088,8 +1088,8 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
 // slices) are only flagged in a bit mask during the walk and scattered
 // afterwards through the general walk_row, so that the lanes of a wave stay
 // on the common path.
-template <typename T, bool Z3, int NCH, bool NONNEG>
-__global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
+template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
+__global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const uint32_t* __restrict__ wmax, double h1,
                                                  double hmax, T* __restrict__ b) {
   // Packed accumulation (float plans, the 4 non-negative AM channels): the
@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(bp_block<Z3>()) __attribute__((amdgpu_waves_per_eu(
   // stays below 2^32 in each half (no carry into the upper half); after every
   // batch each thread moves the words it owns into 64-bit register totals.
   constexpr bool PK = NONNEG && sizeof(T) == 4 && NCH == 4;
-  using BT = BpTile<Z3, NCH, PK>;
+  using BT = BpTile<Z3, NCH, PK, SM>;
   constexpr int RS = BT::tx + 1;       // padded row stride (words)
   constexpr int TXY = RS * BT::ty;     // words per slice
   constexpr int NVOX = TXY * BT::tz;   // words per channel (pair of channels when PK)
@@ -2047,23 +2047,37 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
   return hipGetLastError();
 }
 
-template <typename T, bool Z3, int NCH, bool NONNEG>
-static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
-                        hipStream_t st) {
-  using BT = BpTile<Z3, NCH, NONNEG && sizeof(T) == 4 && NCH == 4>;
+template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
+static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
+                           hipStream_t st) {
+  using BT = BpTile<Z3, NCH, NONNEG && sizeof(T) == 4 && NCH == 4, SM>;
   Tiling TL{BT::tx, BT::ty, BT::tz, 0, 0, 0};
   TL.ntx = (p->gd.nx + BT::tx - 1) / BT::tx;
   TL.nty = (p->gd.ny + BT::ty - 1) / BT::ty;
   TL.ntz = ((Z3 ? p->gd.nz : 1) + BT::tz - 1) / BT::tz;
   const size_t lds = BT::lds_bytes;
   const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
-  auto kern = k_bp<T, Z3, NCH, NONNEG>;
+  auto kern = k_bp<T, Z3, NCH, NONNEG, SM>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nt), dim3(BT::block), lds, st, p->gd, TL, (const T*)w, wmax,
                      p->h1_bound, p->hmax, (T*)b);
   return hipGetLastError();
+}
+
+// 2D: whole-CU 32 x 32 tiles when there are enough of them to give every
+// compute unit one, else 16 x 16 tiles (four per CU)
+template <typename T, bool Z3, int NCH, bool NONNEG>
+static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
+                        hipStream_t st) {
+  if constexpr (Z3) {
+    return bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmax, b, st);
+  } else {
+    const int64_t n32 = (int64_t)((p->gd.nx + 31) / 32) * ((p->gd.ny + 31) / 32);
+    return n32 >= p->n_cu ? bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmax, b, st)
+                          : bp_tiles<T, Z3, NCH, NONNEG, true>(p, w, wmax, b, st);
+  }
 }
 
 template <typename T, bool Z3>

@@ -34,9 +34,26 @@ def odd_helix():
                       col_offset=-0.3, drow_iso=1.5, beta0=0.7, views_per_rot=24.0, feed_per_rot=4.0)
 
 
+def wide_fan():
+    """A 520 x 500 grid: enough 32 x 32 tiles (17 x 16) for the backprojector
+    to take whole-CU tiles, with ragged tiles on two edges; 60 views.
+
+    Mixed plans walk in FP32 grid coordinates relative to the grid corner, so
+    a segment's split point carries an error of about the FP32 spacing at the
+    coordinate (6e-5 pixel at 520).  The errors of a voxel's terms are
+    independent, so a backprojection's relative error grows with the grid
+    extent and falls with the square root of the views per voxel: about 7e-6
+    here, against 7e-7 for 128 x 128 with 180 views."""
+    return G.Geometry(kind=0, nx=520, ny=500, nz=1, dx=0.9, dy=0.95, dz=1.0, n_views=60, n_rows=1,
+                      n_cols=601, sid=600.0, sdd=1100.0,
+                      dgamma=G.fan_dgamma(520, 500, 0.9, 0.95, 600.0, 601), col_offset=0.25,
+                      drow_iso=1.0, beta0=0.4, views_per_rot=60.0, feed_per_rot=0.0)
+
+
 GEOMS = {
     "fan64": lambda: geometry_for("fan64"),
     "fan128": lambda: geometry_for("fan128"),
+    "wide_fan": wide_fan,
     "helical_small": lambda: geometry_for("helical_small"),
     "odd_fan": odd_fan,
     "odd_helix": odd_helix,
@@ -160,6 +177,32 @@ def test_iterate(orc, name, n, prec, tol):
     c = c.cpu().numpy()
     h = hist.cpu().numpy()
     print(name, prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
+    assert rel(c, c_o) <= tol
+    assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_iterate_wide_fan(orc, prec, tol):
+    """Whole-CU backprojector tiles with ragged edges through the iteration
+    (the packed four-channel accumulation), against the oracle."""
+    from workloads.configs import cold_start, expected_counts, surrogate_Z, unrolled_phantom
+    from workloads.phantoms import metal_fraction
+    from workloads.physics import basis_mu, spectra
+    g = wide_fan()
+    I0, mu = spectra(1e5), basis_mu()
+    ph = unrolled_phantom(7, scale=2.0)
+    d = np.random.default_rng(8).poisson(expected_counts(g, ph, I0)).astype(np.float32)
+    metal = (metal_fraction(ph, g, 4) >= 0.5).astype(np.uint8).reshape(-1)
+    mask_o, _ = orc.metal_trace(g, metal, 0.45)
+    assert mask_o.sum() > 0
+    c0, Z, n = cold_start(g, I0), surrogate_Z(g, mu, I0), 5
+    c_o, h_o = orc.iterate(g, I0, mu, d, mask_o, Z, c0, n)
+    plan = plan_for(g, (I0, mu), prec)
+    c = torch.tensor(c0, device=DEV)
+    hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+    plan.iterate(c, torch.tensor(d, device=DEV), torch.tensor(mask_o, device=DEV), Z, n, hist)
+    c, h = c.cpu().numpy(), hist.cpu().numpy()
+    print("wide_fan", prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
     assert rel(c, c_o) <= tol
     assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
 
