@@ -993,6 +993,15 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
   return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
 }
 
+// Non-negative FP64 terms (the AM weights): the same rounding and split
+// without the sign, so the result equals to_fixed(x) for every x >= 0.
+__device__ __forceinline__ unsigned long long to_fixed_nonneg(double x) {
+  const double ax = x + 0.5;
+  const double hi = floor(ax * 2.3283064365386963e-10);
+  const double lo = fma(-hi, 4294967296.0, ax);
+  return ((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo;
+}
+
 // View set-up of a tile for one batch of VB views (all threads of
 // the block take part; three barriers).  For every view of the batch: the
 // channels [kl, kl + nk) whose rays can meet the tile, from the channel
@@ -1190,6 +1199,8 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
             qv[c] = (uint32_t)fmaf((float)da, (float)wa[c], 0.5f);
           else if constexpr (NONNEG && sizeof(T) == 4)
             qv[c] = to_fixed_nonneg((float)da, (float)wa[c]);
+          else if constexpr (NONNEG)
+            qv[c] = to_fixed_nonneg((double)(da * wa[c]));
           else
             qv[c] = to_fixed(da * wa[c]);
         }
