@@ -993,13 +993,12 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
   return x < 0.0 ? (unsigned long long)(-(long long)q) : q;
 }
 
-// Non-negative FP64 terms (the AM weights): the same rounding and split
-// without the sign, so the result equals to_fixed(x) for every x >= 0.
+// Non-negative FP64 terms (the AM weights), kept below 2^51 by their scale:
+// x + 2^52 lies in [2^52, 2^53), where the doubles are the integers, so the
+// addition rounds x to the nearest integer (ties to even) and leaves it in
+// the low 52 bits of the result.
 __device__ __forceinline__ unsigned long long to_fixed_nonneg(double x) {
-  const double ax = x + 0.5;
-  const double hi = floor(ax * 2.3283064365386963e-10);
-  const double lo = fma(-hi, 4294967296.0, ax);
-  return ((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo;
+  return (unsigned long long)__double_as_longlong(x + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
 }
 
 // View set-up of a tile for one batch of VB views (all threads of
@@ -1153,6 +1152,11 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       s = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
     else
       s = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
+    // FP64, non-negative: every term (at most hmax * max|w| * s) below 2^51
+    // for the conversion by addition; h1 >= n_views * hmax, so this binds
+    // only for scans of fewer than 1024 views
+    if (sizeof(T) == 8 && NONNEG && m > 0.f && hmax > 0.0)
+      s = fmin(s, 2251799813685248.0 / (hmax * (double)m));
     scl[c] = (T)fmin(s, 1e30);
   }
 
