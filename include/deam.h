@@ -60,7 +60,7 @@ typedef enum {
   DEAM_ERR_GEOMETRY = -3,    /* the geometry is invalid (e.g. source inside the grid) */
   DEAM_ERR_WORKSPACE = -4,   /* the workspace is too small */
   DEAM_ERR_HIP = -5,         /* a HIP runtime call failed */
-  DEAM_ERR_UNSUPPORTED = -6, /* the request is valid but not supported by this build */
+  DEAM_ERR_UNSUPPORTED = -6, /* the request is valid but not supported by this library */
   DEAM_ERR_VALUE = -7        /* a scalar argument has an invalid value */
 } deam_status;
 

@@ -247,7 +247,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     const double mx = (double)std::max(geom->nx, geom->ny);
     const double bytes = (2.0 * V + mx * mx) * 2.0 * 8.0 + 512.0;
     if (bytes >= 4294967296.0)
-      return fail(DEAM_ERR_UNSUPPORTED, "volume too large for this build (packed images >= 4 GiB)");
+      return fail(DEAM_ERR_UNSUPPORTED, "volume too large for this library (packed images >= 4 GiB)");
   }
   for (int i = 0; i < 2 * n_energy; ++i) {
     if (!(std::isfinite(I0[i]) && I0[i] >= 0.0))
