@@ -1178,7 +1178,14 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       const int loc = it - s_off[j];
       const int nk = s_nk[j];
       const int rr = loc / nk;
-      const int k = s_kl[j] + (loc - rr * nk);
+      // 2D: the view's even channels first, then its odd ones, so that
+      // neighbouring lanes walk rays two channels apart, which rarely meet the
+      // same voxel in the same step (neighbouring channels are about a pixel
+      // apart and often do, and LDS atomics on one address serialise).  In 3D
+      // a wave spans the channels of several (view, row) pairs, and the
+      // contiguous order keeps their chord lengths alike.
+      const int kk = loc - rr * nk, nh = (nk + 1) >> 1;
+      const int k = s_kl[j] + ((Z3 || kk < nh) ? (Z3 ? kk : 2 * kk) : 2 * (kk - nh) + 1);
       const int r = s_rl[j] + rr;
       const int v = G.voff + G.vsub * (vb0 + j);
       Ray<T> ry;
