@@ -1169,7 +1169,19 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
   for (int vb0 = 0; vb0 < G.nvl; vb0 += VB) {
     cull_views<1, VB>(G, vb0, X0, X1, Y0, Y1, Z0, Z1, s_kap, s_kl, s_nk, s_rl, s_nr, s_off);
     const int total = s_off[VB];
-    for (int it = threadIdx.x; it < total; it += NT) {
+    for (int it0 = threadIdx.x; it0 < total; it0 += NT) {
+      // 3D: within each whole block of 64 items (one wave), even items go to
+      // the first 32 lanes and odd ones to the rest, so that neighbouring
+      // lanes walk rays two channels apart (fewer same-address LDS atomics)
+      // while the wave keeps its items and their similar chord lengths
+      int it = it0;
+      if constexpr (Z3) {
+        const int blk = it0 & ~63;
+        if (blk + 64 <= total) {
+          const int l = it0 & 63;
+          it = blk + (l < 32 ? 2 * l : 2 * (l - 32) + 1);
+        }
+      }
       // view of the item: the last j with s_off[j] <= it (binary search)
       int j = 0;
 #pragma unroll
