@@ -100,6 +100,27 @@ def iteration_model(g, S, nE):
     return ops, byt
 
 
+def copy_bandwidth(dev, reps=3):
+    """HBM bytes per second of a plain 1 GiB device-to-device copy (read plus
+    write), the practical ceiling of a streaming kernel; also the reference of
+    the FETCH_SIZE / WRITE_SIZE counter calibration."""
+    import torch
+    n = 1 << 28                       # 2^28 float32 = 1 GiB read and 1 GiB written
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    torch.cuda.empty_cache()
+    return bw, reps + 1
+
+
 def measure(workload, K, W, K64, dev, log, extras=True):
     """Mixed-precision step time, per-kernel times, the all-FP64 step time and
     the roofline figures of one workload (inputs resident in HBM); with
@@ -148,6 +169,24 @@ def measure(workload, K, W, K64, dev, log, extras=True):
     torch.cuda.synchronize()
     t_fp2 = e0.elapsed_time(e1) / K
     grays = g.n_rays / ((t_fp2 + t_bp) * 1e-3) / 1e9
+    # one channel each way (single-image projectors)
+    c1 = cf[:1].contiguous()
+    w1 = plan.forward(c1)
+    plan.backproject(w1)
+    e0.record()
+    for _ in range(K):
+        plan.forward(c1)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fp1 = e0.elapsed_time(e1) / K
+    e0.record()
+    for _ in range(K):
+        plan.backproject(w1)
+    e1.record()
+    torch.cuda.synchronize()
+    t_bp1 = e0.elapsed_time(e1) / K
+    grays1 = g.n_rays / ((t_fp1 + t_bp1) * 1e-3) / 1e9
+    del c1, w1
 
     # all-FP64 variant
     plan64 = Plan(g, inp["I0"], inp["mu"], "fp64")
@@ -273,10 +312,12 @@ def measure(workload, K, W, K64, dev, log, extras=True):
     times = {"fp_poly": t_fp_poly, "backproject": t_bp}
     dom = max(times, key=times.get)
     achieved = ops[dom] / (times[dom] * 1e-3)
+    traffic = read_traffic(dom, workload)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": read_traffic(dom, workload), "kernel": dom, "ops_per_launch": ops[dom],
-                "segments": S, "avg_launch_ms": times[dom]}
+                "traffic": traffic, "kernel": dom, "ops_per_launch": ops[dom],
+                "segments": S, "avg_launch_ms": times[dom],
+                "traffic_GBps": None if traffic is None else traffic / (times[dom] * 1e-3) / 1e9}
     it_ops, it_bytes = iteration_model(g, S, nE)
     t_valu, t_hbm = it_ops / PEAK_LANE_OPS, it_bytes / PEAK_HBM
     iteration = {"valu_model_ms": t_valu * 1e3, "hbm_model_ms": t_hbm * 1e3,
@@ -284,8 +325,9 @@ def measure(workload, K, W, K64, dev, log, extras=True):
                  "frac_of_binding_roofline": max(t_valu, t_hbm) / t_step,
                  "hbm_frac": it_bytes / t_step / PEAK_HBM}
     return dict(inp=inp, plan=plan, d=d, mask=mask, c0=c0, t_step=t_step, grays=grays,
+                grays_1ch=grays1,
                 kernel_ms={"fp_poly": t_fp_poly, "backproject": t_bp, "update": t_upd,
-                           "forward_2ch": t_fp2},
+                           "forward_2ch": t_fp2, "forward_1ch": t_fp1, "backproject_1ch": t_bp1},
                 fp64={"iterations_per_s": 1.0 / t_step64, "ms_per_step": t_step64 * 1e3,
                       "steps": K64},
                 speedup=t_step64 / t_step, roofline=roofline, iteration=iteration,
@@ -370,17 +412,15 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
-        n = 1 << 28                       # 2^28 float32 = 1 GiB read and 1 GiB written
-        x = torch.ones(n, dtype=torch.float32, device=dev)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        bw, launches = copy_bandwidth(dev)
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                          "launches": launches, "copy_GBps": bw / 1e9}))
         return
     K, W = args.steps, args.warmup
     K64 = args.fp64_steps if args.fp64_steps is not None else max(2, K // 4)
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    copy_bw, _ = copy_bandwidth(dev)
+    log(f"device copy: {copy_bw / 1e9:.0f} GB/s (read + write)")
     m = measure(args.workload, K, W, K64, dev, log, extras=not args.no_secondary)
     g, inp, t_step = m["inp"]["geom"], m["inp"], m["t_step"]
     plan, d, mask, c0, Z = m["plan"], m["d"], m["mask"], m["c0"], inp["Z"]
@@ -405,11 +445,13 @@ def main():
                    "energy_bins": int((inp["I0"].sum(axis=0) > 0).sum()),
                    "metal_rays": int(mask.sum().item())},
         "grays_per_s": m["grays"],
+        "grays_per_s_1ch": m["grays_1ch"],
         "kernel_ms": m["kernel_ms"],
         "fp64": m["fp64"],
         "speedup_mixed_vs_fp64": m["speedup"],
         "roofline": m["roofline"],
         "iteration_roofline": m["iteration"],
+        "hbm_copy_GBps": copy_bw / 1e9,
         "penalized": m["penalized"],
         "mar_init": m["mar_init"],
         "variants": m["variants"],
@@ -435,6 +477,15 @@ def main():
                                "sample": f"{n_it} full FP64 oracle DEAM iterations of the {args.workload} "
                                          f"workload from the cold start ({t_cpu:.1f} s)"}
         out["error_vs_oracle"] = {"iterations": n_it, "image_rel_l2": err, "objective_rel": herr}
+        # the same oracle on one core, one iteration
+        n_all = O.num_threads()
+        O.set_num_threads(1)
+        t0 = time.perf_counter()
+        O.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_np, Z, inp["c0"], 1)
+        t_one = time.perf_counter() - t0
+        O.set_num_threads(n_all)
+        out["cpu_baseline"]["one_core"] = {"value": 1.0 / t_one, "unit": "iterations/s", "cores": 1,
+                                           "sample": f"1 FP64 oracle iteration ({t_one:.1f} s)"}
 
     # --- secondary workloads: the 3D helical case and the unrolled reconstruction
     if not args.no_secondary and args.workload != "helical":
@@ -444,6 +495,7 @@ def main():
         out["helical"] = {"workload": f"helical: {WORKLOAD_DESC['helical']}",
                           "iterations_per_s": 1.0 / h["t_step"], "ms_per_step": h["t_step"] * 1e3,
                           "steps": args.helical_steps, "grays_per_s": h["grays"],
+                          "grays_per_s_1ch": h["grays_1ch"],
                           "kernel_ms": h["kernel_ms"], "fp64": h["fp64"],
                           "speedup_mixed_vs_fp64": h["speedup"], "roofline": h["roofline"],
                           "iteration_roofline": h["iteration"], "penalized": h["penalized"]}

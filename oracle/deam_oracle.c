@@ -44,6 +44,7 @@
 /* ----------------------------------------------------------------------- */
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 long orc_n_rays(const orc_geom* g) { return (long)g->n_views * g->n_rows * g->n_cols; }
 long orc_n_voxels(const orc_geom* g) { return (long)g->nx * g->ny * (g->kind == ORC_HELICAL3D ? g->nz : 1); }

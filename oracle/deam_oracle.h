@@ -20,6 +20,9 @@ typedef struct {
 } orc_geom;
 
 int orc_num_threads(void);
+/* threads of the parallel loops that follow (a timing control: only the rounding of the
+ * penalty's parallel sum depends on it) */
+void orc_set_num_threads(int n);
 long orc_n_rays(const orc_geom* g);
 long orc_n_voxels(const orc_geom* g);
 void orc_ray(const orc_geom* g, long ray, double S[3], double P[3]);

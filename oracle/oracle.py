@@ -101,6 +101,7 @@ def _setup(L):
     i1 = P(dtype=np.int64, flags="C_CONTIGUOUS")
     G = C.POINTER(OrcGeom)
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_num_threads.argtypes = [C.c_int]
     L.orc_ray.argtypes = [G, C.c_long, d1, d1]
     L.orc_siddon_ray.argtypes = [G, d1, d1, i1, d1, C.c_int]
     L.orc_siddon_ray.restype = C.c_int
@@ -148,6 +149,11 @@ def _setup(L):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def geom_struct(g):
