@@ -1,8 +1,8 @@
 """Parity at the benchmark sizes, with the launch configuration bench.py times.
 
 fan512 (2D, 512^2, 984 x 816 rays): the oracle runs the whole problem: metal
-mask (bit-exact), forward projection, backprojection and two full DEAM
-iterations.  helical (512^2 x 64, 4608 x 16 x 816 rays): the oracle computes
+mask (bit-exact), forward projection, backprojection, two full DEAM iterations
+and the 20 iterations of the stated image tolerance.  helical (512^2 x 64, 4608 x 16 x 816 rays): the oracle computes
 sampled rays one by one (line integrals, metal trace, expected counts);
 properties that hold at any size (adjoint identity, monotone objective) cover
 the rest."""
@@ -61,6 +61,29 @@ def test_fan512_full(orc, fan512):
     print("fan512 2-iteration image rel", rel(c.cpu().numpy(), c_o))
     assert rel(c.cpu().numpy(), c_o) <= 1e-5
     assert np.abs(hist.cpu().numpy() - h_o).max() <= 1e-6 * h_o[0]
+
+
+def test_fan512_20_iterations_against_oracle(orc, fan512):
+    """The stated image tolerance at the benchmark size: 20 DEAM iterations
+    from the cold start, both GPU precisions against the oracle's 20
+    iterations on the same inputs (image and objective history)."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = fan512
+    g = inp["geom"]
+    n = 20
+    mask_o, _ = orc.metal_trace(g, inp["metal"], inp["t"])
+    c_o, h_o = orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], inp["c0"], n)
+    d = torch.tensor(inp["d"], device=DEV)
+    mask = torch.tensor(mask_o, device=DEV)
+    for prec, tol, htol in (("mixed", 1e-4, 1e-5), ("fp64", 1e-10, 1e-10)):
+        plan = Plan(g, inp["I0"], inp["mu"], prec)
+        c = torch.tensor(inp["c0"], device=DEV)
+        hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+        plan.iterate(c, d, mask, inp["Z"], n, hist)
+        e = rel(c.cpu().numpy(), c_o)
+        eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
+        print(f"fan512 {prec} 20 iterations: image rel {e:.3e}, objective rel {eh:.3e}")
+        assert e <= tol and eh <= htol
 
 
 def test_fan512_objective_monotone_50_iterations(fan512):
