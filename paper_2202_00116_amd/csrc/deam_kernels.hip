@@ -37,6 +37,8 @@ namespace {
 template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
+// two packed float pixels read by one 16-byte load at an 8-byte boundary
+typedef float Pix2f __attribute__((ext_vector_type(4), aligned(8)));
 
 // clamp to [lo, hi] in one v_med3_i32 (the compiler emits min + max)
 __device__ __forceinline__ int clampi(int v, int lo, int hi) {
@@ -334,17 +336,31 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)C * plane) * E;
   int q = qlo;
   int groups = 0;
-  for (; q + 4 <= qhi; q += 4) {
-    uint32_t oA[4], oB[4];
-    T dA[4], dB[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) step(q + s, oA[s], oB[s], dA[s], dB[s]);
+  // the two pixels of a step.  2D float plans: they are neighbours in one
+  // row (|A - B| <= 1), so one 16-byte load at the lower offset fetches both
+  // (at the last pixel of a copy it also reads the next element, inside the
+  // next copy or the zeroed tail, and does not use it)
+  auto load2 = [&](uint32_t oA, uint32_t oB, T2& vA, T2& vB) {
+    if constexpr (!Z3 && sizeof(T) == 4) {
+      const uint32_t om = min(oA, oB);
+      const Pix2f v = *(const Pix2f*)(cpb + om);
+      T2 lo, hi;
+      lo.x = v.x;
+      lo.y = v.y;
+      hi.x = v.z;
+      hi.y = v.w;
+      vA = (oA == om) ? lo : hi;
+      vB = (oB == om) ? lo : hi;
+    } else {
+      vA = *(const T2*)(cpb + oA);
+      vB = *(const T2*)(cpb + oB);
+    }
+  };
+  // gathers and sums of four steps: all gathers before the sums
+  auto accumulate4 = [&](const uint32_t* oA, const uint32_t* oB, const T* dA, const T* dB) {
     T2 vA[4], vB[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      vA[s] = *(const T2*)(cpb + oA[s]);
-      vB[s] = *(const T2*)(cpb + oB[s]);
-    }
+    for (int s = 0; s < 4; ++s) load2(oA[s], oB[s], vA[s], vB[s]);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       p1 = fma(dA[s], vA[s].x, p1);
@@ -352,26 +368,102 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
       p1 = fma(dB[s], vB[s].x, p1);
       p2 = fma(dB[s], vB[s].y, p2);
     }
-    ++groups;
-    if ((groups & 3) == 0) flush();
-    if constexpr (Z3) {
-      if ((groups & 15) == 0) {
-        fixup();
-        qw = q + 4;
-      }
-    }
-  }
-  for (; q < qhi; ++q) {
-    uint32_t oA, oB;
-    T dA, dB;
-    step(q, oA, oB, dA, dB);
-    const T2 vA = *(const T2*)(cpb + oA), vB = *(const T2*)(cpb + oB);
+  };
+  auto accumulate1 = [&](uint32_t oA, uint32_t oB, T dA, T dB) {
+    T2 vA, vB;
+    load2(oA, oB, vA, vB);
     p1 = fma(dA, vA.x, p1);
     p2 = fma(dA, vA.y, p2);
     p1 = fma(dB, vB.x, p1);
     p2 = fma(dB, vB.y, p2);
+  };
+  // plane steps [q, qe) through the general step
+  auto general = [&](int qe) {
+    for (; q + 4 <= qe; q += 4) {
+      uint32_t oA[4], oB[4];
+      T dA[4], dB[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) step(q + s, oA[s], oB[s], dA[s], dB[s]);
+      accumulate4(oA, oB, dA, dB);
+      ++groups;
+      if ((groups & 3) == 0) flush();
+      if constexpr (Z3) {
+        if ((groups & 15) == 0) {
+          fixup();
+          qw = q + 4;
+        }
+      }
+    }
+    for (; q < qe; ++q) {
+      uint32_t oA, oB;
+      T dA, dB;
+      step(q, oA, oB, dA, dB);
+      accumulate1(oA, oB, dA, dB);
+    }
+  };
+  if constexpr (Z3) {
+    general(qhi);
+    fixup();
+  } else {
+    // 2D: plane steps [qa, qb) lie inside the chord of every lane that has a
+    // ray, so each is a whole plane spacing.  There the walk is Siddon's
+    // incremental form: e is the distance (in plane spacings) from the start
+    // of the step to the next lateral plane, and a step with e < 1 splits
+    // there and moves one pixel in the direction sg.  e is recomputed from the
+    // ray's line every 16 steps, which bounds its rounding drift.  Lanes
+    // without a ray (zero ray: sg = 0) stay on pixel 0 of the rows walked.
+    const int qa = max(wave_max(hit ? -ifloor(-ry.alo) : qlo), qlo);
+    const int qb = min(wave_min(hit ? ifloor(ry.ahi) : qhi), qhi);
+    if (qa >= qb) {
+      general(qhi);
+    } else {
+      general(qa);
+      flush();
+      const int sg = ry.mb > (T)0 ? 1 : (ry.mb < (T)0 ? -1 : 0);
+      const T iab = fabs(ry.imb), iab1 = iab - (T)1;
+      T e = 0;
+      auto sync = [&]() {
+        bp = fma((T)q, ry.mb, ry.b0);
+        A = clampi(ifloor(bp), 0, nb - 1);
+        e = sg > 0 ? ((T)(A + 1) - bp) * iab : (sg < 0 ? (bp - (T)A) * iab : (T)1e30);
+      };
+      auto istep = [&](uint32_t& oA, uint32_t& oB, T& dA, T& dB) {
+        const bool cr = e < (T)1;
+        dA = clampf(e, (T)0, (T)1);
+        dB = (T)1 - dA;
+        const int B = clampi(A + (cr ? sg : 0), 0, nb - 1);
+        oA = row + (uint32_t)A * E;
+        oB = row + (uint32_t)B * E;
+        row += rstep;
+        e += cr ? iab1 : (T)-1;
+        A = B;
+      };
+      sync();
+      for (; q + 4 <= qb; q += 4) {
+        if (q != qa && ((q - qa) & 15) == 0) {
+          flush();
+          sync();
+        }
+        uint32_t oA[4], oB[4];
+        T dA[4], dB[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) istep(oA[s], oB[s], dA[s], dB[s]);
+        accumulate4(oA, oB, dA, dB);
+      }
+      for (; q < qb; ++q) {
+        uint32_t oA, oB;
+        T dA, dB;
+        istep(oA, oB, dA, dB);
+        accumulate1(oA, oB, dA, dB);
+      }
+      flush();
+      // back to the general step at plane qb
+      fa = (T)qb;
+      tp = (T)qb;
+      sync();
+      general(qhi);
+    }
   }
-  if constexpr (Z3) fixup();
   flush();
   if (hit) {
     l1 = (s1 + c1) * ry.La;
