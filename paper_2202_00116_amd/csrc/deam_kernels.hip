@@ -927,9 +927,23 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           C[j] = D;
           zo[j] = slice_off(D);
         }
-        // one 32-bit offset from the uniform base (SGPR-based addressing)
-        vA[j] = *(const T2*)(cpb + (uint32_t)(oA + zo[j]));
-        vB[j] = *(const T2*)(cpb + (uint32_t)(oB + zo[j]));
+        // one 32-bit offset from the uniform base (SGPR-based addressing).
+        // Float plans: the two pixels are neighbours in one row, so one
+        // 16-byte load at the lower offset fetches both (the element after a
+        // row's last pixel lies in the next row, copy or the zeroed tail)
+        if constexpr (sizeof(T) == 4) {
+          const Pix2f v2 = *(const Pix2f*)(cpb + (uint32_t)(min(oA, oB) + zo[j]));
+          T2 lo, hi;
+          lo.x = v2.x;
+          lo.y = v2.y;
+          hi.x = v2.z;
+          hi.y = v2.w;
+          vA[j] = oA <= oB ? lo : hi;
+          vB[j] = oB <= oA ? lo : hi;
+        } else {
+          vA[j] = *(const T2*)(cpb + (uint32_t)(oA + zo[j]));
+          vB[j] = *(const T2*)(cpb + (uint32_t)(oB + zo[j]));
+        }
       }
 #pragma unroll
       for (int j = 0; j < RG; ++j) {
