@@ -336,46 +336,59 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)C * plane) * E;
   int q = qlo;
   int groups = 0;
-  // the two pixels of a step.  2D float plans: they are neighbours in one
-  // row (|A - B| <= 1), so one 16-byte load at the lower offset fetches both
-  // (at the last pixel of a copy it also reads the next element, inside the
-  // next copy or the zeroed tail, and does not use it)
-  auto load2 = [&](uint32_t oA, uint32_t oB, T2& vA, T2& vB) {
-    if constexpr (!Z3 && sizeof(T) == 4) {
-      const uint32_t om = min(oA, oB);
-      const Pix2f v = *(const Pix2f*)(cpb + om);
-      T2 lo, hi;
-      lo.x = v.x;
-      lo.y = v.y;
-      hi.x = v.z;
-      hi.y = v.w;
-      vA = (oA == om) ? lo : hi;
-      vB = (oB == om) ? lo : hi;
-    } else {
-      vA = *(const T2*)(cpb + oA);
-      vB = *(const T2*)(cpb + oB);
-    }
-  };
-  // gathers and sums of four steps: all gathers before the sums
+  // gathers and sums of four steps: all gathers before the sums.  2D float
+  // plans: the two pixels of a step are neighbours in one row (|A - B| <= 1),
+  // so one 16-byte load at the lower offset fetches both, and the step's two
+  // lengths are matched to the lower and upper pixel instead (when A = B
+  // the upper length is 0; the element after a copy's last pixel lies in the
+  // next copy or the zeroed tail, so it is finite)
+  constexpr bool PAIR = !Z3 && sizeof(T) == 4;
   auto accumulate4 = [&](const uint32_t* oA, const uint32_t* oB, const T* dA, const T* dB) {
-    T2 vA[4], vB[4];
+    if constexpr (PAIR) {
+      Pix2f v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) load2(oA[s], oB[s], vA[s], vB[s]);
+      for (int s = 0; s < 4; ++s) v[s] = *(const Pix2f*)(cpb + min(oA[s], oB[s]));
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      p1 = fma(dA[s], vA[s].x, p1);
-      p2 = fma(dA[s], vA[s].y, p2);
-      p1 = fma(dB[s], vB[s].x, p1);
-      p2 = fma(dB[s], vB[s].y, p2);
+      for (int s = 0; s < 4; ++s) {
+        const bool al = oA[s] <= oB[s];
+        const T dl = al ? dA[s] : dB[s], dh = al ? dB[s] : dA[s];
+        p1 = fma(dl, v[s].x, p1);
+        p2 = fma(dl, v[s].y, p2);
+        p1 = fma(dh, v[s].z, p1);
+        p2 = fma(dh, v[s].w, p2);
+      }
+    } else {
+      T2 vA[4], vB[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        vA[s] = *(const T2*)(cpb + oA[s]);
+        vB[s] = *(const T2*)(cpb + oB[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        p1 = fma(dA[s], vA[s].x, p1);
+        p2 = fma(dA[s], vA[s].y, p2);
+        p1 = fma(dB[s], vB[s].x, p1);
+        p2 = fma(dB[s], vB[s].y, p2);
+      }
     }
   };
   auto accumulate1 = [&](uint32_t oA, uint32_t oB, T dA, T dB) {
-    T2 vA, vB;
-    load2(oA, oB, vA, vB);
-    p1 = fma(dA, vA.x, p1);
-    p2 = fma(dA, vA.y, p2);
-    p1 = fma(dB, vB.x, p1);
-    p2 = fma(dB, vB.y, p2);
+    if constexpr (PAIR) {
+      const Pix2f v = *(const Pix2f*)(cpb + min(oA, oB));
+      const bool al = oA <= oB;
+      const T dl = al ? dA : dB, dh = al ? dB : dA;
+      p1 = fma(dl, v.x, p1);
+      p2 = fma(dl, v.y, p2);
+      p1 = fma(dh, v.z, p1);
+      p2 = fma(dh, v.w, p2);
+    } else {
+      const T2 vA = *(const T2*)(cpb + oA), vB = *(const T2*)(cpb + oB);
+      p1 = fma(dA, vA.x, p1);
+      p2 = fma(dA, vA.y, p2);
+      p1 = fma(dB, vB.x, p1);
+      p2 = fma(dB, vB.y, p2);
+    }
   };
   // plane steps [q, qe) through the general step
   auto general = [&](int qe) {
@@ -918,7 +931,6 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
       const uint32_t oA = row + (uint32_t)A * E, oB = row + (uint32_t)B * E;
       row += rstep;
       const T un = (tn - t.sa) * t.ida;
-      T2 vA[RG], vB[RG];
 #pragma unroll
       for (int j = 0; j < RG; ++j) {
         const int D = ifloor(fma(un, zr[j], sw));
@@ -927,28 +939,37 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           C[j] = D;
           zo[j] = slice_off(D);
         }
-        // one 32-bit offset from the uniform base (SGPR-based addressing).
-        // Float plans: the two pixels are neighbours in one row, so one
-        // 16-byte load at the lower offset fetches both (the element after a
-        // row's last pixel lies in the next row, copy or the zeroed tail)
-        if constexpr (sizeof(T) == 4) {
-          const Pix2f v2 = *(const Pix2f*)(cpb + (uint32_t)(min(oA, oB) + zo[j]));
-          T2 lo, hi;
-          lo.x = v2.x;
-          lo.y = v2.y;
-          hi.x = v2.z;
-          hi.y = v2.w;
-          vA[j] = oA <= oB ? lo : hi;
-          vB[j] = oB <= oA ? lo : hi;
-        } else {
+      }
+      // one 32-bit offset from the uniform base (SGPR-based addressing).
+      // Float plans: the two pixels are neighbours in one row, so one 16-byte
+      // load at the lower offset fetches both, and the two lengths are matched
+      // to the lower and upper pixel once for all rows (when A = B the upper
+      // length is 0; the element after a row's last pixel lies in the next
+      // row, copy or the zeroed tail, so it is finite)
+      if constexpr (sizeof(T) == 4) {
+        const uint32_t om = min(oA, oB);
+        const bool al = oA <= oB;
+        const T dl = al ? dA : dB, dh = al ? dB : dA;
+        Pix2f v2[RG];
+#pragma unroll
+        for (int j = 0; j < RG; ++j) v2[j] = *(const Pix2f*)(cpb + (uint32_t)(om + zo[j]));
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+          p1[j] = fma(dl, v2[j].x, fma(dh, v2[j].z, p1[j]));
+          p2[j] = fma(dl, v2[j].y, fma(dh, v2[j].w, p2[j]));
+        }
+      } else {
+        T2 vA[RG], vB[RG];
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
           vA[j] = *(const T2*)(cpb + (uint32_t)(oA + zo[j]));
           vB[j] = *(const T2*)(cpb + (uint32_t)(oB + zo[j]));
         }
-      }
 #pragma unroll
-      for (int j = 0; j < RG; ++j) {
-        p1[j] = fma(dA, vA[j].x, fma(dB, vB[j].x, p1[j]));
-        p2[j] = fma(dA, vA[j].y, fma(dB, vB[j].y, p2[j]));
+        for (int j = 0; j < RG; ++j) {
+          p1[j] = fma(dA, vA[j].x, fma(dB, vB[j].x, p1[j]));
+          p2[j] = fma(dA, vA[j].y, fma(dB, vB[j].y, p2[j]));
+        }
       }
       A = B;
       bp = bn;
