@@ -50,6 +50,16 @@ def wide_fan():
                       drow_iso=1.0, beta0=0.4, views_per_rot=60.0, feed_per_rot=0.0)
 
 
+def axis_fan():
+    """Degenerate rays: an odd channel count with no offset and views every
+    45 degrees from 0, so the central channel runs exactly along an axis
+    (slope 0, on a pixel boundary of the even grid) or exactly along a
+    diagonal through pixel corners (slope 1)."""
+    return G.Geometry(kind=0, nx=48, ny=48, nz=1, dx=1.0, dy=1.0, dz=1.0, n_views=8, n_rows=1,
+                      n_cols=65, sid=200.0, sdd=400.0, dgamma=G.fan_dgamma(48, 48, 1.0, 1.0, 200.0, 65),
+                      col_offset=0.0, drow_iso=1.0, beta0=0.0, views_per_rot=8.0, feed_per_rot=0.0)
+
+
 GEOMS = {
     "fan64": lambda: geometry_for("fan64"),
     "fan128": lambda: geometry_for("fan128"),
@@ -205,6 +215,54 @@ def test_iterate_wide_fan(orc, prec, tol):
     print("wide_fan", prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
     assert rel(c, c_o) <= tol
     assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_degenerate_rays(orc, spectra, prec, tol):
+    """Rays along the grid's central lines and diagonals.  A ray within
+    rounding of a grid line may run in either adjacent row (the crossing of an
+    almost parallel line is ill-conditioned), so what is compared is what does
+    not depend on that choice: line integrals of an image that is symmetric
+    about both central lines, backprojections away from the central rows and
+    columns, sums of mirror pairs on them, and the adjoint identity (the
+    forward and backward walks must choose alike)."""
+    g = axis_fan()
+    plan = plan_for(g, spectra, prec)
+    rng = np.random.default_rng(41)
+    img = rng.uniform(0, 1, (2, g.ny, g.nx))
+    img = img + img[:, ::-1, :]
+    img = img + img[:, :, ::-1]
+    img = img.reshape(2, -1)
+    if prec == "mixed":
+        img = img.astype(np.float32).astype(np.float64)
+    l = plan.forward(torch.tensor(img, dtype=plan.dtype, device=DEV)).cpu().numpy()
+    assert rel(l, orc.forward(g, img)) <= tol
+    w = rng.uniform(0, 1, (1, g.n_rays))
+    if prec == "mixed":
+        w = w.astype(np.float32).astype(np.float64)
+    b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()[0].reshape(g.ny, g.nx)
+    b_o = orc.backproject(g, w)[0].reshape(g.ny, g.nx)
+    hy, hx = g.ny // 2, g.nx // 2
+    off = np.ones((g.ny, g.nx), bool)
+    off[hy - 1:hy + 1, :] = False
+    off[:, hx - 1:hx + 1] = False
+    scale = np.abs(b_o).max()
+    assert np.abs(b - b_o)[off].max() <= tol * 10 * scale
+    # rows hy-1, hy in pairs (away from the central columns), columns hx-1, hx
+    # in pairs (away from the central rows), and the 2 x 2 centre as a whole
+    cols = np.r_[0:hx - 1, hx + 1:g.nx]
+    rows = np.r_[0:hy - 1, hy + 1:g.ny]
+    rp, rp_o = b[hy - 1:hy + 1, cols].sum(0), b_o[hy - 1:hy + 1, cols].sum(0)
+    cp, cp_o = b[rows, hx - 1:hx + 1].sum(1), b_o[rows, hx - 1:hx + 1].sum(1)
+    assert np.abs(rp - rp_o).max() <= tol * 10 * scale
+    assert np.abs(cp - cp_o).max() <= tol * 10 * scale
+    centre, centre_o = b[hy - 1:hy + 1, hx - 1:hx + 1].sum(), b_o[hy - 1:hy + 1, hx - 1:hx + 1].sum()
+    assert abs(centre - centre_o) <= tol * 10 * scale
+    x = torch.tensor(rng.uniform(0, 1, (1, g.n_voxels)), dtype=plan.dtype, device=DEV)
+    y = torch.tensor(rng.uniform(0, 1, (1, g.n_rays)), dtype=plan.dtype, device=DEV)
+    lhs = (plan.forward(x).double() * y.double()).sum().item()
+    rhs = (x.double() * plan.backproject(y).double()).sum().item()
+    assert abs(lhs - rhs) <= (1e-5 if prec == "mixed" else 1e-12) * abs(lhs)
 
 
 def test_iterate_is_deterministic_and_resumable(spectra):
