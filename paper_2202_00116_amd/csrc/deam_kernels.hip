@@ -705,8 +705,8 @@ __device__ void block_reduce(double term, const float wabs[4], int nch, double* 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <typename T, bool Z3, int MODE>
 // 2D float plans: eight waves per SIMD (64 VGPRs, no spills)
+template <typename T, bool Z3, int MODE>
 __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !Z3 ? 8 : 1))) void k_fp(
     GeomDev G, const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff,
     const EBin<T>* __restrict__ eb, int nE,
