@@ -265,6 +265,46 @@ def test_degenerate_rays(orc, spectra, prec, tol):
     assert abs(lhs - rhs) <= (1e-5 if prec == "mixed" else 1e-12) * abs(lhs)
 
 
+def random_fan(seed):
+    """A seeded 2D fan: grids of 3 to 90 pixels a side, anisotropic pixels, a
+    random channel offset and start angle, few to many views and channels.
+    Short chords, empty common interiors of a wave and chords that start or
+    end on the wave's first or last plane all occur."""
+    r = np.random.default_rng(seed)
+    nx, ny = int(r.integers(3, 91)), int(r.integers(3, 91))
+    dx, dy = float(r.uniform(0.5, 1.5)), float(r.uniform(0.5, 1.5))
+    n_cols = int(r.integers(7, 200))
+    n_views = int(r.integers(3, 40))
+    rad = 0.5 * np.hypot(nx * dx, ny * dy)
+    sid = float(r.uniform(1.5, 6.0)) * rad
+    sdd = sid + rad * float(r.uniform(1.1, 3.0))      # the detector lies beyond the grid
+    return G.Geometry(kind=0, nx=nx, ny=ny, nz=1, dx=dx, dy=dy, dz=1.0, n_views=n_views, n_rows=1,
+                      n_cols=n_cols, sid=sid, sdd=sdd,
+                      dgamma=G.fan_dgamma(nx, ny, dx, dy, sid, n_cols) * float(r.uniform(0.7, 1.2)),
+                      col_offset=float(r.uniform(-0.5, 0.5)), drow_iso=1.0,
+                      beta0=float(r.uniform(0, 2 * np.pi)), views_per_rot=float(r.uniform(n_views, 2 * n_views)),
+                      feed_per_rot=0.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_random_fans(orc, spectra, prec, tol):
+    """Forward and backprojection on 12 seeded random fans against the oracle."""
+    for seed in range(200, 212):
+        g = random_fan(seed)
+        plan = plan_for(g, spectra, prec)
+        rng = np.random.default_rng(seed)
+        c = rng.uniform(0, 1, (2, g.n_voxels))
+        w = rng.uniform(0, 1, (2, g.n_rays))
+        if prec == "mixed":
+            c = c.astype(np.float32).astype(np.float64)
+            w = w.astype(np.float32).astype(np.float64)
+        l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
+        b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
+        el, eb = rel(l, orc.forward(g, c)), rel(b, orc.backproject(g, w))
+        print(f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}: forward {el:.2e}, backproject {eb:.2e}")
+        assert el <= tol and eb <= tol, seed
+
+
 def test_iterate_is_deterministic_and_resumable(spectra):
     inp = make_inputs("fan64")
     g = inp["geom"]
