@@ -305,6 +305,49 @@ def test_random_fans(orc, spectra, prec, tol):
         assert el <= tol and eb <= tol, seed
 
 
+def random_helix(seed):
+    """A seeded helical scan: grids of 4 to 48 pixels a side and 2 to 14
+    slices, 1 to 9 detector rows, a feed of up to a collimation per turn (or
+    none), random offsets and start angle."""
+    r = np.random.default_rng(seed)
+    nx, ny, nz = int(r.integers(4, 49)), int(r.integers(4, 49)), int(r.integers(2, 15))
+    dx, dy, dz = float(r.uniform(0.6, 1.4)), float(r.uniform(0.6, 1.4)), float(r.uniform(0.6, 1.6))
+    n_rows, n_cols = int(r.integers(1, 10)), int(r.integers(9, 120))
+    n_views = int(r.integers(8, 60))
+    rad = 0.5 * np.hypot(nx * dx, ny * dy)
+    sid = float(r.uniform(1.5, 6.0)) * rad
+    sdd = sid + rad * float(r.uniform(1.1, 3.0))
+    drow = float(r.uniform(0.5, 2.0))
+    vpr = float(r.uniform(0.3 * n_views, n_views))
+    feed = 0.0 if seed % 4 == 0 else float(r.uniform(0.2, 1.0)) * n_rows * drow
+    return G.Geometry(kind=1, nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, n_views=n_views,
+                      n_rows=n_rows, n_cols=n_cols, sid=sid, sdd=sdd,
+                      dgamma=G.fan_dgamma(nx, ny, dx, dy, sid, n_cols) * float(r.uniform(0.8, 1.2)),
+                      col_offset=float(r.uniform(-0.5, 0.5)), drow_iso=drow,
+                      beta0=float(r.uniform(0, 2 * np.pi)), views_per_rot=vpr, feed_per_rot=feed)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_random_helices(orc, spectra, prec, tol):
+    """Forward and backprojection on 8 seeded random helical scans against
+    the oracle."""
+    for seed in range(300, 308):
+        g = random_helix(seed)
+        plan = plan_for(g, spectra, prec)
+        rng = np.random.default_rng(seed)
+        c = rng.uniform(0, 1, (2, g.n_voxels))
+        w = rng.uniform(0, 1, (2, g.n_rays))
+        if prec == "mixed":
+            c = c.astype(np.float32).astype(np.float64)
+            w = w.astype(np.float32).astype(np.float64)
+        l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
+        b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
+        el, eb = rel(l, orc.forward(g, c)), rel(b, orc.backproject(g, w))
+        print(f"seed {seed} {g.nx}x{g.ny}x{g.nz} {g.n_views}x{g.n_rows}x{g.n_cols} {prec}: "
+              f"forward {el:.2e}, backproject {eb:.2e}")
+        assert el <= tol and eb <= tol, seed
+
+
 def test_iterate_is_deterministic_and_resumable(spectra):
     inp = make_inputs("fan64")
     g = inp["geom"]
