@@ -305,6 +305,34 @@ def test_random_fans(orc, spectra, prec, tol):
         assert el <= tol and eb <= tol, seed
 
 
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_random_fans_iterate(orc, prec, tol):
+    """Three DEAM iterations (the packed four-channel backprojection) on four
+    seeded random fans, data from a phantom scaled to the grid, against the
+    oracle."""
+    from workloads.configs import cold_start, expected_counts, surrogate_Z, unrolled_phantom
+    from workloads.phantoms import metal_fraction
+    from workloads.physics import basis_mu, spectra as make_spectra
+    I0, mu = make_spectra(1e5), basis_mu()
+    for seed in range(220, 224):
+        g = random_fan(seed)
+        ph = unrolled_phantom(seed, scale=0.45 * min(g.nx * g.dx, g.ny * g.dy) / 90.0)
+        d = np.random.default_rng(seed).poisson(expected_counts(g, ph, I0)).astype(np.float32)
+        metal = (metal_fraction(ph, g, 4) >= 0.5).astype(np.uint8).reshape(-1)
+        mask_o, _ = orc.metal_trace(g, metal, 0.5 * min(g.dx, g.dy))
+        c0, Z, n = cold_start(g, I0), surrogate_Z(g, mu, I0), 3
+        c_o, h_o = orc.iterate(g, I0, mu, d, mask_o, Z, c0, n)
+        plan = plan_for(g, (I0, mu), prec)
+        c = torch.tensor(c0, device=DEV)
+        hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+        plan.iterate(c, torch.tensor(d, device=DEV), torch.tensor(mask_o, device=DEV), Z, n, hist)
+        e = rel(c.cpu().numpy(), c_o)
+        eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
+        print(f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}: image {e:.2e}, "
+              f"objective {eh:.2e}, trace rays {int(mask_o.sum())}")
+        assert e <= tol and eh <= (1e-5 if prec == "mixed" else 1e-9), seed
+
+
 def random_helix(seed):
     """A seeded helical scan: grids of 4 to 48 pixels a side and 2 to 14
     slices, 1 to 9 detector rows, a feed of up to a collimation per turn (or
