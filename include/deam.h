@@ -128,6 +128,11 @@ int deam_plan_set_bowtie(deam_plan* plan, const double* bt);
 int deam_plan_sizes(const deam_plan* plan, int64_t* n_rays, int64_t* n_voxels);
 /* Bytes of device workspace needed by an operation (deam_op). */
 int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes);
+/* The same size for a plan of this geometry and precision, computed without
+ * a plan or a device (to size a workspace before creating the plan).  Equal
+ * to deam_workspace_size of the plan that deam_plan_create would make. */
+int deam_workspace_size_for(const deam_geometry* geom, int32_t precision, int32_t op,
+                            size_t* bytes);
 
 /* Metal trace (Section 2.1, Eqs. 2-3): T(y) = sum_x h(x,y) M(x) in FP64 for
  * both precisions, and mask[y] = (T(y) >= t).

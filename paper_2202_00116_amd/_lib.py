@@ -22,6 +22,7 @@ STATUS = {0: "DEAM_OK", -1: "DEAM_ERR_NULL", -2: "DEAM_ERR_SHAPE", -3: "DEAM_ERR
           -7: "DEAM_ERR_VALUE"}
 
 EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_workspace_size",
+           "deam_workspace_size_for",
            "deam_metal_trace", "deam_forward", "deam_poly_mean", "deam_backproject",
            "deam_update", "deam_iterate", "deam_iterate_timed", "deam_iterate_vjp",
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
@@ -69,6 +70,7 @@ def load():
         "deam_plan_destroy": [vp],
         "deam_plan_sizes": [vp, C.POINTER(i64), C.POINTER(i64)],
         "deam_workspace_size": [vp, i32, C.POINTER(sz)],
+        "deam_workspace_size_for": [G, i32, i32, C.POINTER(sz)],
         "deam_metal_trace": [vp, vp, dp, vp, vp, vp, sz, vp],
         "deam_forward": [vp, vp, i32, vp, vp, sz, vp],
         "deam_poly_mean": [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp],

@@ -132,6 +132,34 @@ void fill_energy(std::vector<unsigned char>& out, int& nE, int n_energy, const d
   std::memcpy(out.data(), bins.data(), out.size());
 }
 
+// The size fields of a plan (grid, detector, ray and block counts): all that
+// the workspace layout depends on, computed from the geometry alone.
+void fill_plan_sizes(deam_plan* p, const deam_geometry& g, int precision) {
+  const bool is3d = g.kind == DEAM_HELICAL3D;
+  p->g = g;
+  p->precision = precision;
+  deam::GeomDev& G = p->gd;
+  G.is3d = is3d ? 1 : 0;
+  G.nx = g.nx;
+  G.ny = g.ny;
+  G.nz = is3d ? g.nz : 1;
+  G.n_views = g.n_views;
+  G.n_rows = g.n_rows;
+  G.n_cols = g.n_cols;
+  G.voff = 0;
+  G.vsub = 1;
+  G.nvl = g.n_views;
+  G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
+  G.V = (int64_t)g.nx * g.ny * G.nz;
+  p->ray_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
+  if (is3d) {
+    const int rg = precision == DEAM_PREC_FP64 ? deam::fp3_rows<double>() : deam::fp3_rows<float>();
+    p->fp_blocks = deam::fp3_blocks(g.n_views, g.n_rows, g.n_cols, rg);
+  } else {
+    p->fp_blocks = p->ray_blocks;
+  }
+}
+
 }  // namespace
 
 namespace deam {
@@ -148,13 +176,14 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
   };
   const size_t nblk = (size_t)p->fp_blocks;
   // The packed image copies: natural order, then (with no gap) x-major order,
-  // then max(nx, ny)^2 zeroed elements.  The forward projector's lanes walk a
-  // common range of plane rows; a lane outside its own range reads, with zero
-  // weight, rows up to max(nx, ny) of its copy, which stay inside this region
-  // and hold finite values.
-  const size_t mx = (size_t)std::max(p->gd.nx, p->gd.ny);
+  // then packed_tail_elems zeroed elements.  The forward projector's lanes
+  // walk a common range of plane rows; a lane outside its own range reads,
+  // with zero weight, rows up to max(nx, ny) of its copy, and a row outside
+  // the slices reads the tail; every such read stays inside this region and
+  // finds finite values.
+  const size_t tail = packed_tail_elems(p->gd.nx, p->gd.ny);
   auto take_packed = [&](size_t es) {
-    L.cp_y = take((2 * V + mx * mx) * es);
+    L.cp_y = take((2 * V + tail) * es);
     L.cp_x = L.cp_y + V * es;
   };
   switch (op) {
@@ -244,8 +273,8 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     // the second) with 32-bit byte offsets; the metal trace packs in FP64 on
     // every plan
     const double V = (double)geom->nx * geom->ny * (geom->kind == DEAM_HELICAL3D ? geom->nz : 1);
-    const double mx = (double)std::max(geom->nx, geom->ny);
-    const double bytes = (2.0 * V + mx * mx) * 2.0 * 8.0 + 512.0;
+    const double tail = (double)deam::packed_tail_elems(geom->nx, geom->ny);
+    const double bytes = (2.0 * V + tail) * 2.0 * 8.0 + 512.0;
     if (bytes >= 4294967296.0)
       return fail(DEAM_ERR_UNSUPPORTED, "volume too large for this library (packed images >= 4 GiB)");
   }
@@ -260,8 +289,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
 
   deam_plan* p = new (std::nothrow) deam_plan();
   if (!p) return fail(DEAM_ERR_VALUE, "out of host memory");
-  p->g = g;
-  p->precision = precision;
+  fill_plan_sizes(p, g, precision);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(DEAM_ERR_HIP, "hipGetDevice failed");
@@ -382,16 +410,6 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   }
 
   deam::GeomDev& G = p->gd;
-  G.is3d = is3d ? 1 : 0;
-  G.nx = g.nx;
-  G.ny = g.ny;
-  G.nz = is3d ? g.nz : 1;
-  G.n_views = g.n_views;
-  G.n_rows = g.n_rows;
-  G.n_cols = g.n_cols;
-  G.voff = 0;
-  G.vsub = 1;
-  G.nvl = g.n_views;
   G.dx = g.dx;
   G.dy = g.dy;
   G.dz = g.dz;
@@ -410,8 +428,6 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   G.rays64 = (const deam::RayXY<double>*)p->d_rays64;
   G.bowtie = nullptr;
   G.mbits = nullptr;
-  G.R = (int64_t)g.n_views * g.n_rows * g.n_cols;
-  G.V = (int64_t)g.nx * g.ny * G.nz;
 
   p->d_fbp = fbp_ok ? G.row + (size_t)g.n_rows * 4 : nullptr;
   // photons per ray and spectrum-weighted attenuation (Eq. 4's weights)
@@ -438,13 +454,6 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   }
   p->h1_bound = h1_bound(g);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
-  p->ray_blocks = (G.R + deam::kFpBlock - 1) / deam::kFpBlock;
-  if (g.kind == DEAM_HELICAL3D) {
-    const int rg = precision == DEAM_PREC_FP64 ? deam::fp3_rows<double>() : deam::fp3_rows<float>();
-    p->fp_blocks = deam::fp3_blocks(g.n_views, g.n_rows, g.n_cols, rg);
-  } else {
-    p->fp_blocks = p->ray_blocks;
-  }
   *out = p;
   return ok();
 }
@@ -500,6 +509,20 @@ int deam_workspace_size(const deam_plan* plan, int32_t op, size_t* bytes) {
   if (op < DEAM_OP_FORWARD || op > DEAM_OP_MAR_INIT)
     return fail(DEAM_ERR_VALUE, "unknown op %d", op);
   *bytes = deam::workspace_layout(plan, op).total;
+  return ok();
+}
+
+int deam_workspace_size_for(const deam_geometry* geom, int32_t precision, int32_t op,
+                            size_t* bytes) {
+  if (!bytes) return fail(DEAM_ERR_NULL, "bytes is NULL");
+  if (int rc = validate_geometry(geom)) return rc;
+  if (precision != DEAM_PREC_MIXED && precision != DEAM_PREC_FP64)
+    return fail(DEAM_ERR_VALUE, "unknown precision %d", precision);
+  if (op < DEAM_OP_FORWARD || op > DEAM_OP_MAR_INIT)
+    return fail(DEAM_ERR_VALUE, "unknown op %d", op);
+  deam_plan q{};
+  fill_plan_sizes(&q, *geom, precision);
+  *bytes = deam::workspace_layout(&q, op).total;
   return ok();
 }
 

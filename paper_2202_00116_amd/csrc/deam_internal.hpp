@@ -105,6 +105,18 @@ inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
 constexpr int kViewBatch = 128;
 constexpr int kMaxFbpCols = 4096;   // FBP filter: one detector row of p and g in LDS (64 KiB)
 
+// Elements of the zeroed tail that follows the two packed image copies.  The
+// lanes of a forward-projector wave walk a common range of plane rows q <
+// max(nx, ny), so a lane whose row lies outside the slices (3D) reads the
+// tail at in-plane element q * nb + A <= max(nx, ny) * nb - 1 (nb, the
+// lateral extent, is nx or ny), and float plans fetch the pixel after that
+// one too (one 16-byte load per pixel pair): at most max(nx, ny)^2 + 1
+// elements, rounded up to keep 16-byte multiples.
+inline size_t packed_tail_elems(int nx, int ny) {
+  const size_t mx = (size_t)(nx > ny ? nx : ny);
+  return mx * mx + 2;
+}
+
 // Workspace pieces (byte offsets, 256-aligned).
 struct WsLayout {
   size_t cp_y, cp_x;     // packed projection images (natural and transposed)

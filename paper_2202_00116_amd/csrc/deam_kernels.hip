@@ -945,8 +945,11 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
       // Float plans: the two pixels are neighbours in one row, so one 16-byte
       // load at the lower offset fetches both, and the two lengths are matched
       // to the lower and upper pixel once for all rows (when A = B the upper
-      // length is 0; the element after a row's last pixel lies in the next
-      // row, copy or the zeroed tail, so it is finite)
+      // length is 0).  The element after the lower pixel is the next one in
+      // its row, the first of the next row or copy, or, for a row outside the
+      // slices, an element of the zeroed tail, which is sized for the pixel
+      // after the last one a lane can address (packed_tail_elems): finite
+      // and in bounds)
       if constexpr (sizeof(T) == 4) {
         const uint32_t om = min(oA, oB);
         const bool al = oA <= oB;
@@ -2086,15 +2089,15 @@ hipError_t launch_pack(const deam_plan* p, const void* c, int n_ch, bool from_u8
   return launch_zero_tail(p, cp_x, dbl, st);
 }
 
-// Zero the max(nx,ny)^2 elements after the x-major copy (which follows the
-// natural copy with no gap): the forward projectors read them for rays
+// Zero the packed_tail_elems elements after the x-major copy (which follows
+// the natural copy with no gap): the forward projectors read them for rays
 // outside the slices and for idle lanes, so they must hold zeros (0 x NaN
 // would not vanish).
 hipError_t launch_zero_tail(const deam_plan* p, void* cp_x, bool dbl, hipStream_t st) {
   const size_t e2 = dbl ? sizeof(double2) : sizeof(float2);
-  const int64_t mx = max(p->gd.nx, p->gd.ny);
+  const size_t n = packed_tail_elems(p->gd.nx, p->gd.ny);
   return launch_fill_u32((uint32_t*)((char*)cp_x + (size_t)p->gd.V * e2), 0u,
-                         (int64_t)((size_t)mx * (size_t)mx * e2 / 4), st);
+                         (int64_t)(n * e2 / 4), st);
 }
 
 template <typename T, int MODE>

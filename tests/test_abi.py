@@ -92,3 +92,40 @@ def test_null_plan_calls(lib):
     assert lib.deam_poly_mean(None, None, None, None, 0, None, None, None, None, None, 0, None) == -1
     assert lib.deam_metal_trace(None, None, 0.5, None, None, None, 0, None) == -1
     assert b"NULL" in lib.deam_last_error()
+
+
+@pytest.mark.parametrize("kind,nx,ny,nz", [
+    (0, 64, 64, 1), (0, 80, 48, 1), (0, 48, 80, 1),
+    (1, 64, 64, 16), (1, 96, 40, 8), (1, 40, 96, 8), (1, 512, 512, 64),
+])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_packed_region_covers_every_forward_read(lib, kind, nx, ny, nz, prec):
+    """The forward projectors read the packed image region: the natural copy
+    (V pixel pairs), the x-major copy (V pairs) and a zeroed tail.  The lanes
+    of a wave walk a common range of plane rows q <= max(nx, ny) - 1, so a
+    ray whose row lies outside the slices reads the tail at pair 2V + q*nb +
+    A with A <= nb - 1 (nb = nx or ny, the lateral extent), and float plans
+    load the pair after it as well (one 16-byte load per pixel pair).  The
+    region that the workspace query reserves must hold every such pair."""
+    g = geometry(kind=kind, nx=nx, ny=ny, nz=nz, n_rows=4 if kind else 1,
+                 dx=0.5, dy=0.5, dz=0.5, drow_iso=1.0)
+    V = nx * ny * nz
+    mx = max(nx, ny)
+    pair = 8 if prec == 0 else 16          # bytes per packed pixel pair
+    extra = 1 if prec == 0 else 0          # the paired load's upper pixel
+    need = max((2 * V + mx * nb - 1 + extra + 1) * pair for nb in (nx, ny))
+    n = C.c_size_t()
+    assert lib.deam_workspace_size_for(C.byref(g), prec, 0, C.byref(n)) == 0   # DEAM_OP_FORWARD
+    assert n.value >= need, (n.value, need)
+    # the metal trace packs FP64 pairs on every plan and reads them one by one
+    assert lib.deam_workspace_size_for(C.byref(g), prec, 4, C.byref(n)) == 0
+    assert n.value >= max((2 * V + mx * nb) * 16 for nb in (nx, ny))
+
+
+def test_workspace_size_for_rejects_bad_arguments(lib):
+    n = C.c_size_t()
+    assert lib.deam_workspace_size_for(None, 0, 0, C.byref(n)) == -1
+    assert lib.deam_workspace_size_for(C.byref(geometry()), 0, 0, None) == -1
+    assert lib.deam_workspace_size_for(C.byref(geometry(nx=0)), 0, 0, C.byref(n)) == -2
+    assert lib.deam_workspace_size_for(C.byref(geometry()), 2, 0, C.byref(n)) == -7
+    assert lib.deam_workspace_size_for(C.byref(geometry()), 0, 99, C.byref(n)) == -7
