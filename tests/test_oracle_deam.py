@@ -191,3 +191,29 @@ def test_gradient_matches_finite_differences(orc):
     fp = orc.objective(g, inp["I0"], inp["mu"], inp["d"], mask, c + h * e)
     fm = orc.objective(g, inp["I0"], inp["mu"], inp["d"], mask, c - h * e)
     assert abs((fp - fm) / (2 * h) - np.sum(grad * e)) <= 1e-5 * np.abs(grad).max()
+
+
+def test_vjp_weights_are_finite_difference_products(orc):
+    """W_VJP (adjoint of Eq. 8 for an upstream v_j = dloss/dg_j): the weight
+    u_i(y) equals sum_j v_j dg_j/dl_i, with dg_j/dl_i taken by central
+    differences of the oracle's expected counts g in l_i (not by the energy
+    sums a_ij that the mode uses).  The trace does not enter."""
+    inp = make_inputs("fan64", with_data=False)
+    I0, mu = inp["I0"], inp["mu"]
+    rng = np.random.default_rng(23)
+    R = 400
+    l = rng.uniform(0, 25, (2, R))
+    v = rng.standard_normal((2, R))
+    d = rng.uniform(0, 1e5, (2, R))
+    mask = (rng.random(R) < 0.3).astype(np.uint8)
+    u, _, _ = orc.poly_mean(I0, mu, l, d, mask, mode=orc.W_VJP, v=v)
+    h = 1e-3
+    for i in range(2):
+        lp, lm = l.copy(), l.copy()
+        lp[i] += h
+        lm[i] -= h
+        _, gp, _ = orc.poly_mean(I0, mu, lp, d)
+        _, gm, _ = orc.poly_mean(I0, mu, lm, d)
+        fd = (v * (gp - gm)).sum(axis=0) / (2 * h)
+        scale = (np.abs(v) * np.abs(gp - gm)).sum(axis=0) / (2 * h)
+        assert np.all(np.abs(u[i] - fd) <= 1e-6 * scale + 1e-12), i

@@ -158,9 +158,11 @@ def test_adjoint_identity(orc, name):
     assert abs(lhs - rhs) <= 1e-12 * (np.abs(orc.forward(g, np.abs(x))).sum() * np.abs(y).max())
 
 
-def test_backprojection_matches_dense_transpose(orc):
-    """The oracle backprojector equals the transpose of the brute-force dense H."""
-    g = small_fan()
+@pytest.mark.parametrize("geom_fn", [small_fan, small_box3d])
+def test_backprojection_matches_dense_transpose(orc, geom_fn):
+    """The oracle backprojector equals the transpose of the brute-force dense H
+    (2D fan and a 3D helical box)."""
+    g = geom_fn()
     S, P = ray_endpoints(g)
     H = np.stack([ray_row(g, S[i], P[i]) for i in range(g.n_rays)])
     rng = np.random.default_rng(7)
@@ -168,3 +170,19 @@ def test_backprojection_matches_dense_transpose(orc):
     assert np.allclose(orc.backproject(g, w)[0], H.T @ w, atol=1e-11)
     c = rng.standard_normal(g.n_voxels)
     assert np.allclose(orc.forward(g, c)[0], H @ c, atol=1e-11)
+
+
+@pytest.mark.parametrize("name", ["fan64", "helical_small"])
+def test_forward_rays_equals_forward(orc, name):
+    """The sampled-ray projector (the reference of the full-size checks) returns,
+    bit for bit, the selected columns of the whole-sinogram projection, for a
+    ray list in arbitrary order with repeats and both ends of the range."""
+    from workloads import geometry_for
+    g = geometry_for(name)
+    rng = np.random.default_rng(17)
+    img = rng.standard_normal((2, g.n_voxels))
+    full = orc.forward(g, img)
+    rays = np.concatenate([[g.n_rays - 1, 0], rng.integers(0, g.n_rays, 500), [7, 7]])
+    sel = orc.forward_rays(g, img, rays)
+    assert sel.shape == (2, rays.size)
+    assert np.array_equal(sel, full[:, rays])

@@ -80,6 +80,15 @@ MUTATIONS = {
     "os_subset_order": ("if ((y / per_view) % n_sub != s)", "if ((y / per_view) % n_sub != (s + 1) % n_sub)"),
     "os_no_restriction": ("if ((y / per_view) % n_sub != s)", "if (0)"),
     "os_history_at_last_subset": ("if (s == 0 && obj_hist) obj_hist[k]", "if (obj_hist) obj_hist[k]"),
+    "vjp_weight_sign": ("w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][1]);",
+                        "w[(long)i * R + y] = (v[y] * a[i][0] + v[R + y] * a[i][1]);"),
+    "vjp_spectrum_index": ("w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][1]);",
+                           "w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][0]);"),
+    "vjp_upstream_swap": ("w[(long)i * R + y] = -(v[y] * a[i][0] + v[R + y] * a[i][1]);",
+                          "w[(long)i * R + y] = -(v[R + y] * a[i][0] + v[y] * a[i][1]);"),
+    "forward_rays_ignores_list": ("orc_ray(g, rays[s], S, P);", "orc_ray(g, s, S, P);"),
+    "forward_rays_layout": ("out[(long)k * n_sel + s] = nval(&acc);",
+                            "out[(long)s * nch + k] = nval(&acc);"),
     "pen_history_without_penalty": (
         "obj_hist[k] = orc_sum(R, obj) + orc_penalty(g, c, lambda, delta);",
         "obj_hist[k] = orc_sum(R, obj);"),
@@ -115,6 +124,8 @@ PINS = [
     lambda o: Du.test_same_scans_are_deam(o),
     lambda o: Du.test_dilate_mask(o),
     lambda o: Bt.test_filter_is_a_shift_of_the_line_integrals(o, "am"),
+    lambda o: D.test_vjp_weights_are_finite_difference_products(o),
+    lambda o: Gm.test_forward_rays_equals_forward(o, "fan64"),
 ]
 
 
