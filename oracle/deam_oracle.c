@@ -72,9 +72,20 @@ void orc_ray(const orc_geom* g, long ray, double S[3], double P[3]) {
 /* Siddon's method on the grid, restricted to the voxel sub-box [lo, hi).   */
 /* ----------------------------------------------------------------------- */
 
-static int cmp_double(const void* a, const void* b) {
-  double x = *(const double*)a, y = *(const double*)b;
-  return (x > y) - (x < y);
+/* Merge the ascending runs run[0..nrun) (run r is src[beg[r]..end[r])) into
+ * dst, behind dst[0], in ascending order (Siddon's merge of the parametric
+ * crossing sets of the three axes). */
+static int merge_runs(const double* src, const int* beg, const int* end, int nrun,
+                      double* dst, int m) {
+  int pos[3] = {0, 0, 0};
+  for (int r = 0; r < nrun; ++r) pos[r] = beg[r];
+  for (;;) {
+    int best = -1;
+    for (int r = 0; r < nrun; ++r)
+      if (pos[r] < end[r] && (best < 0 || src[pos[r]] < src[pos[best]])) best = r;
+    if (best < 0) return m;
+    dst[m++] = src[pos[best]++];
+  }
 }
 
 int orc_siddon(const orc_geom* g, const double S[3], const double P[3],
@@ -105,9 +116,12 @@ int orc_siddon(const orc_geom* g, const double S[3], const double P[3],
   }
   if (!(amax > amin)) return 0;
 
-  /* all plane crossings strictly inside (amin, amax) */
-  int m = 0;
-  scratch[m++] = amin;
+  /* all plane crossings strictly inside (amin, amax), one ascending run per
+     axis (alpha grows with the plane index when D > 0 and falls when D < 0,
+     and the rounded values keep that order), merged into the sorted list
+     amin, crossings..., amax in the second half of scratch */
+  int n_in = 0, nrun = 0;
+  int beg[3], end[3];
   for (int a = 0; a < naxes; ++a) {
     if (D[a] == 0.0) continue;
     double s = S[a];
@@ -119,17 +133,23 @@ int orc_siddon(const orc_geom* g, const double S[3], const double P[3],
     int i1 = (int)ceil((xb - org[a]) / dlt[a]) + 1;
     if (i0 < lo[a] + 1) i0 = lo[a] + 1;
     if (i1 > hi[a] - 1) i1 = hi[a] - 1;
-    for (int i = i0; i <= i1; ++i) {
+    beg[nrun] = n_in;
+    for (int k = 0; k <= i1 - i0; ++k) {
+      int i = D[a] > 0.0 ? i0 + k : i1 - k;
       double al = (org[a] + i * dlt[a] - s) / D[a];
-      if (al > amin && al < amax) scratch[m++] = al;
+      if (al > amin && al < amax) scratch[n_in++] = al;
     }
+    end[nrun++] = n_in;
   }
-  scratch[m++] = amax;
-  qsort(scratch, (size_t)m, sizeof(double), cmp_double);
+  double* list = scratch + n_in;
+  int m = 0;
+  list[m++] = amin;
+  m = merge_runs(scratch, beg, end, nrun, list, m);
+  list[m++] = amax;
 
   int cnt = 0;
   for (int q = 0; q + 1 < m; ++q) {
-    double a0 = scratch[q], a1 = scratch[q + 1];
+    double a0 = list[q], a1 = list[q + 1];
     if (!(a1 > a0)) continue;                       /* coincident crossings */
     double am = 0.5 * (a0 + a1);
     int iv[3] = {0, 0, 0};
@@ -159,7 +179,7 @@ int orc_siddon_ray(const orc_geom* g, const double S[3], const double P[3],
                    long* idx, double* len, int cap) {
   int lo[3] = {0, 0, 0};
   int hi[3] = {g->nx, g->ny, g->kind == ORC_HELICAL3D ? g->nz : 1};
-  double* scratch = (double*)malloc(sizeof(double) * (size_t)(max_segments(g) + 4));
+  double* scratch = (double*)malloc(sizeof(double) * (size_t)(2 * (max_segments(g) + 4)));
   int c = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
   free(scratch);
   return c;
@@ -188,7 +208,7 @@ void orc_forward(const orc_geom* g, int nch, const double* img, double* sino) {
   {
     long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
     double* len = (double*)malloc(sizeof(double) * (size_t)cap);
-    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(2 * (cap + 4)));
 #pragma omp for schedule(dynamic, 256)
     for (long y = 0; y < R; ++y) {
       double S[3], P[3];
@@ -215,7 +235,7 @@ void orc_forward_rays(const orc_geom* g, int nch, const double* img, long n_sel,
   {
     long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
     double* len = (double*)malloc(sizeof(double) * (size_t)cap);
-    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(2 * (cap + 4)));
 #pragma omp for schedule(dynamic, 64)
     for (long s = 0; s < n_sel; ++s) {
       double S[3], P[3];
@@ -233,9 +253,56 @@ void orc_forward_rays(const orc_geom* g, int nch, const double* img, long n_sel,
 
 /* ----------------------------------------------------------------------- */
 /* Backprojection img_k(x) = sum_y h(x,y) sino_k(y): the transpose of the   */
-/* forward projection.  Each task owns a band of rows iy and walks every    */
-/* ray clipped to that band, so the sums are deterministic without atomics. */
+/* forward projection.  Each task owns a band of rows iy (3D: one slice iz) */
+/* and walks every ray clipped to that band, so the sums are deterministic  */
+/* without atomics.  The band's bounding planes are crossings of the whole  */
+/* ray, computed with the same expression, so a ray's segments inside the   */
+/* band are those of the whole ray, and each voxel adds its rays in the     */
+/* order of the ray index in either band shape.                             */
 /* ----------------------------------------------------------------------- */
+
+/* 3D: the task of slice iz walks only the detector rows whose segment S->P
+ * reaches that slice (S and P bound the segment's z, and rows that cannot
+ * reach it would be clipped away by orc_siddon anyway); every other ray is
+ * walked exactly as in 2D, so the sums do not depend on the band shape. */
+static void backproject_slabs(const orc_geom* g, int nch, const double* sino, double* img) {
+  long R = orc_n_rays(g), V = orc_n_voxels(g);
+  int cap = max_segments(g);
+  double z0 = -0.5 * g->nz * g->dz;
+  double dzeta = g->drow_iso * g->sdd / g->sid;
+#pragma omp parallel
+  {
+    long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
+    double* len = (double*)malloc(sizeof(double) * (size_t)cap);
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(2 * (cap + 4)));
+#pragma omp for schedule(dynamic, 1)
+    for (int iz = 0; iz < g->nz; ++iz) {
+      int lo[3] = {0, 0, iz};
+      int hi[3] = {g->nx, g->ny, iz + 1};
+      /* the slab with a margin far above rounding: the test only skips rows */
+      double zlo = z0 + iz * g->dz - 1e-6 * g->dz, zhi = z0 + (iz + 1) * g->dz + 1e-6 * g->dz;
+      for (long v = 0; v < g->n_views; ++v) {
+        double zs = ((double)v - 0.5 * (g->n_views - 1)) * g->feed_per_rot / g->views_per_rot;
+        for (long r = 0; r < g->n_rows; ++r) {
+          double zp = zs + ((double)r - 0.5 * (g->n_rows - 1)) * dzeta;
+          if ((zs < zlo && zp < zlo) || (zs > zhi && zp > zhi)) continue;
+          for (long k = 0; k < g->n_cols; ++k) {
+            long y = (v * g->n_rows + r) * g->n_cols + k;
+            double S[3], P[3];
+            orc_ray(g, y, S, P);
+            int n = orc_siddon(g, S, P, lo, hi, idx, len, cap, scratch);
+            for (int c = 0; c < nch; ++c) {
+              double w = sino[(long)c * R + y];
+              if (w == 0.0) continue;
+              for (int q = 0; q < n; ++q) img[(long)c * V + idx[q]] += len[q] * w;
+            }
+          }
+        }
+      }
+    }
+    free(idx); free(len); free(scratch);
+  }
+}
 
 void orc_backproject(const orc_geom* g, int nch, const double* sino, double* img) {
   long R = orc_n_rays(g), V = orc_n_voxels(g);
@@ -243,11 +310,15 @@ void orc_backproject(const orc_geom* g, int nch, const double* sino, double* img
   int band = 4;
   int nbands = (g->ny + band - 1) / band;
   memset(img, 0, sizeof(double) * (size_t)(nch * V));
+  if (g->kind == ORC_HELICAL3D && g->nz >= 8) {
+    backproject_slabs(g, nch, sino, img);
+    return;
+  }
 #pragma omp parallel
   {
     long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
     double* len = (double*)malloc(sizeof(double) * (size_t)cap);
-    double* scratch = (double*)malloc(sizeof(double) * (size_t)(cap + 4));
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(2 * (cap + 4)));
 #pragma omp for schedule(dynamic, 1)
     for (int b = 0; b < nbands; ++b) {
       int lo[3] = {0, b * band, 0};

@@ -26,6 +26,7 @@ void orc_set_num_threads(int n);
 long orc_n_rays(const orc_geom* g);
 long orc_n_voxels(const orc_geom* g);
 void orc_ray(const orc_geom* g, long ray, double S[3], double P[3]);
+/* scratch: 2 * (nx + ny + nz + 12) doubles */
 int orc_siddon(const orc_geom* g, const double S[3], const double P[3],
                const int lo[3], const int hi[3], long* idx, double* len, int cap,
                double* scratch);
