@@ -40,8 +40,11 @@
  *
  * Errors: every function returns a deam_status; on failure deam_last_error()
  * gives a message (thread-local).  Argument checks happen before anything is
- * enqueued; a device fault shows up at the next synchronisation.  Input data
- * values are not checked on the hot path.
+ * enqueued; a device fault shows up at the next synchronisation (and is
+ * returned by deam_iterate_sync).  Input data values are not checked on the
+ * hot path: image values must be finite and counts d finite and >= 0 (the
+ * backprojection of the DEAM weights relies on their signs; a negative count
+ * gives undefined results); deam_validate_inputs checks this on request.
  */
 #ifndef DEAM_H
 #define DEAM_H
@@ -158,7 +161,7 @@ int deam_forward(const deam_plan* plan, const void* c, int32_t n_ch, void* l, vo
 /* Per-ray polyenergetic mean (Eq. 8) with the metal-trace substitution
  * (Eq. 11: p = q where mask = 1) and the weights that feed the backprojection.
  *   l     [2][R] real   line integrals of the two components;
- *   d     [2][R] float  measured counts of the low and high spectrum;
+ *   d     [2][R] float  measured counts of the low and high spectrum (finite, >= 0);
  *   mask  [R]    uint8  corrupt rays (NULL = none);
  *   mode  deam_wmode;
  *   v     [2][R] real   upstream dloss/dg (DEAM_W_VJP only, else NULL);
@@ -174,15 +177,29 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
                    int32_t mode, const void* v, void* w, void* g, double* obj, void* ws,
                    size_t ws_bytes, void* stream);
 
-/* Backprojection with the transpose of the forward operator:
- * b[c][x] = sum_y h(x,y) w[c][y].   w [n_ch][R] real; b [n_ch][V] real; n_ch = 1, 2 or 4.
+/* Backprojection with the transpose of the system operator of Eq. 8 (the
+ * same h(x,y) as deam_forward): b[c][x] = sum_y h(x,y) w[c][y].  With the
+ * DEAM weights of deam_poly_mean it gives b~_i and b^_i of the component
+ * update, and with the GRAD or VJP weights the gradient of Eq. 5's
+ * objective.
+ *   w [n_ch][R] real; b [n_ch][V] real output; n_ch = 1, 2 or 4;
+ *   flags: 0, or DEAM_BP_NONNEG when every weight is >= 0 (as the AM weights
+ *   are): a cheaper rounding, and for 4 channels of a MIXED plan the packed
+ *   accumulation of deam_iterate (two channels per LDS word).  A negative
+ *   weight under DEAM_BP_NONNEG gives undefined results.
  * Accumulation is exact integer (fixed point) per voxel, so results are
  * bitwise reproducible.  Workspace: deam_workspace_size(DEAM_OP_BACKPROJECT). */
-int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b, void* ws,
-                     size_t ws_bytes, void* stream);
+enum { DEAM_BP_NONNEG = 1 };
+int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, int32_t flags, void* b,
+                     void* ws, size_t ws_bytes, void* stream);
 
-/* Component update: for each voxel and i = 1, 2, where b~_i > 0 and b^_i > 0,
+/* Component update, the c-step of DEAM: the minimiser of the surrogate of the
+ * I-divergence (Eq. 5) for the p of Eqs. 9-10 (and p = q on the trace, Eq. 11
+ * and the sentence after it), obtained from the convexity of exp in Eq. 8.
+ * For each voxel and i = 1, 2, where b~_i > 0 and b^_i > 0,
  * c_i <- c_i - ln(b~_i / b^_i) / Z_i (FP64); other voxels are unchanged.
+ * Z_i must satisfy sum_i sum_x h(x,y) mu_i(E) / Z_i <= 1 for every ray y and
+ * energy E with photons (then the objective does not increase).
  *   c64  [2][V] double, updated in place;
  *   b    [4][V] real (b~1, b~2, b^1, b^2) from deam_backproject;
  *   Z    host [2] double, > 0;
@@ -190,17 +207,39 @@ int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b
 int deam_update(const deam_plan* plan, double* c64, void* c_proj, const void* b,
                 const double* Z, void* stream);
 
-/* n_iter DEAM iterations on one stream with no host synchronisation:
- * forward projection + poly-mean (AM), backprojection, update.
+/* n_iter iterations of MAR-DEAM (Section 2.3: Eqs. 5, 8-10, with the data on
+ * the metal trace replaced by the estimate in every iteration, Eq. 11 and the
+ * sentence after it) on one stream with no host synchronisation: forward
+ * projection + poly-mean (AM), backprojection, update.
  *   c64   [2][V] double, updated in place;
- *   d     [2][R] float counts;  mask [R] uint8 or NULL;  Z host [2];
+ *   c_proj [2][V] real output or NULL: the final iterate in the plan precision;
+ *   d     [2][R] float counts (finite, >= 0);  mask [R] uint8 or NULL;  Z host [2];
  *   obj_hist  device [n_iter] double or NULL: obj_hist[k] = masked
  *             I-divergence (Eq. 5 restricted to T < t) at the iterate c^k
  *             entering iteration k.
- * Workspace: deam_workspace_size(DEAM_OP_ITERATE). */
-int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
-                 const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
-                 void* stream);
+ * A device fault shows up at the caller's next synchronisation; the history
+ * stays on the device so that nothing waits (deam_iterate_sync copies it out
+ * and reports faults).  Workspace: deam_workspace_size(DEAM_OP_ITERATE). */
+int deam_iterate(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                 const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* deam_iterate with the objective history in host memory: obj_hist host
+ * [n_iter] double or NULL.  Synchronises `stream` before returning and
+ * returns DEAM_ERR_HIP when a device fault occurred during the iterations.
+ * Allocates n_iter doubles of device memory for the duration of the call. */
+int deam_iterate_sync(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                      const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Debug check of the inputs of an iteration (not on the hot path): c64 [2][V]
+ * double must be finite, d [2][R] float finite and >= 0 (either pointer may
+ * be NULL to skip it).  n_bad host [2] int64 output or NULL: the number of
+ * offending entries of each.  ws: device workspace of >= 16 bytes, 8-byte
+ * aligned (any workspace of the plan's operations qualifies).  Synchronises
+ * `stream`; returns DEAM_ERR_VALUE when an entry is invalid. */
+int deam_validate_inputs(const deam_plan* plan, const double* c64, const float* d, int64_t* n_bad,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* deam_iterate with per-kernel device timing, for benchmarks and profiling.
  * Same arguments and results as deam_iterate, plus
@@ -211,9 +250,9 @@ int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8
  *              [2] the update kernel,
  *              [3] the whole loop (first to last event).
  * Synchronises `stream` before returning. */
-int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
-                       const double* Z, int32_t n_iter, double* obj_hist, void* ws,
-                       size_t ws_bytes, void* stream, float* kernel_ms);
+int deam_iterate_timed(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                       const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                       void* ws, size_t ws_bytes, void* stream, float* kernel_ms);
 
 /* DEAM with a system operator and a metal trace per scan (Section 2.1: the
  * two scans may differ, e.g. by geometry or motion, and then need their own

@@ -269,7 +269,6 @@ static void backproject_slabs(const orc_geom* g, int nch, const double* sino, do
   long R = orc_n_rays(g), V = orc_n_voxels(g);
   int cap = max_segments(g);
   double z0 = -0.5 * g->nz * g->dz;
-  double dzeta = g->drow_iso * g->sdd / g->sid;
 #pragma omp parallel
   {
     long* idx = (long*)malloc(sizeof(long) * (size_t)cap);
@@ -282,10 +281,11 @@ static void backproject_slabs(const orc_geom* g, int nch, const double* sino, do
       /* the slab with a margin far above rounding: the test only skips rows */
       double zlo = z0 + iz * g->dz - 1e-6 * g->dz, zhi = z0 + (iz + 1) * g->dz + 1e-6 * g->dz;
       for (long v = 0; v < g->n_views; ++v) {
-        double zs = ((double)v - 0.5 * (g->n_views - 1)) * g->feed_per_rot / g->views_per_rot;
         for (long r = 0; r < g->n_rows; ++r) {
-          double zp = zs + ((double)r - 0.5 * (g->n_rows - 1)) * dzeta;
-          if ((zs < zlo && zp < zlo) || (zs > zhi && zp > zhi)) continue;
+          /* S and P of every channel of (v, r) share their z */
+          double S0[3], P0[3];
+          orc_ray(g, (v * g->n_rows + r) * g->n_cols, S0, P0);
+          if ((S0[2] < zlo && P0[2] < zlo) || (S0[2] > zhi && P0[2] > zhi)) continue;
           for (long k = 0; k < g->n_cols; ++k) {
             long y = (v * g->n_rows + r) * g->n_cols + k;
             double S[3], P[3];

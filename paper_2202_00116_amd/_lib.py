@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdeam.so")
 FAN2D, HELICAL3D = 0, 1
 PREC_MIXED, PREC_FP64 = 0, 1
 W_AM, W_GRAD, W_VJP, W_STEP_VJP = 0, 1, 2, 3
+BP_NONNEG = 1
 OP_FORWARD, OP_POLY_MEAN, OP_BACKPROJECT, OP_ITERATE, OP_METAL_TRACE, OP_ITERATE_VJP = 0, 1, 2, 3, 4, 5
 OP_PENALTY, OP_ITERATE_PENALIZED, OP_FBP, OP_MAR_INIT = 6, 7, 8, 9
 
@@ -28,7 +29,7 @@ EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_wor
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
            "deam_fbp", "deam_nmar", "deam_mar_init", "deam_iterate_os", "deam_dual_workspace_size",
            "deam_iterate_dual", "deam_dilate_mask", "deam_plan_set_bowtie", "deam_pack_mask",
-           "deam_iterate_packed", "deam_last_error")
+           "deam_iterate_packed", "deam_iterate_sync", "deam_validate_inputs", "deam_last_error")
 
 
 class DeamGeometry(C.Structure):
@@ -74,10 +75,12 @@ def load():
         "deam_metal_trace": [vp, vp, dp, vp, vp, vp, sz, vp],
         "deam_forward": [vp, vp, i32, vp, vp, sz, vp],
         "deam_poly_mean": [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp],
-        "deam_backproject": [vp, vp, i32, vp, vp, sz, vp],
+        "deam_backproject": [vp, vp, i32, i32, vp, vp, sz, vp],
         "deam_update": [vp, vp, vp, vp, vp, vp],
-        "deam_iterate": [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
-        "deam_iterate_timed": [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp, vp],
+        "deam_iterate": [vp, vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
+        "deam_iterate_sync": [vp, vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],
+        "deam_validate_inputs": [vp, vp, vp, vp, vp, sz, vp],
+        "deam_iterate_timed": [vp, vp, vp, vp, vp, vp, i32, vp, vp, sz, vp, vp],
         "deam_iterate_vjp": [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp],
         "deam_penalty": [vp, vp, dp, dp, vp, vp, sz, vp],
         "deam_update_penalized": [vp, vp, vp, vp, vp, vp, dp, dp, vp],

@@ -591,19 +591,20 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
   return ok();
 }
 
-int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, void* b, void* ws,
-                     size_t ws_bytes, void* stream) {
+int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, int32_t flags, void* b,
+                     void* ws, size_t ws_bytes, void* stream) {
   if (int rc = check_plan(plan)) return rc;
   if (!w || !b) return fail(DEAM_ERR_NULL, "w or b is NULL");
   if (n_ch != 1 && n_ch != 2 && n_ch != 4)
     return fail(DEAM_ERR_SHAPE, "n_ch must be 1, 2 or 4 (got %d)", n_ch);
+  if (flags & ~DEAM_BP_NONNEG) return fail(DEAM_ERR_VALUE, "unknown flags 0x%x", (unsigned)flags);
   deam::WsLayout L;
   if (int rc = check_ws(plan, DEAM_OP_BACKPROJECT, ws, ws_bytes, L)) return rc;
   hipStream_t st = (hipStream_t)stream;
   uint32_t* wmax = (uint32_t*)((char*)ws + L.wmax);
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
   HIP_TRY(deam::launch_absmax(plan, w, n_ch, wmax, st));
-  HIP_TRY(deam::launch_backproject(plan, w, n_ch, false, wmax, b, st));
+  HIP_TRY(deam::launch_backproject(plan, w, n_ch, (flags & DEAM_BP_NONNEG) != 0, wmax, b, st));
   return ok();
 }
 
@@ -660,9 +661,9 @@ struct PenSpec {
   double lambda, delta;
 };
 
-static int iterate_impl(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
-                        const double* Z, int32_t n_iter, double* obj_hist, void* ws,
-                        size_t ws_bytes, void* stream, float* kernel_ms,
+static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                        const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                        void* ws, size_t ws_bytes, void* stream, float* kernel_ms,
                         const PenSpec* pen = nullptr) {
   if (int rc = check_plan(plan)) return rc;
   if (!c64 || !d || !Z) return fail(DEAM_ERR_NULL, "c64, d or Z is NULL");
@@ -707,7 +708,9 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
     }                                                                                      \
   } while (0)
   // projection copies of the starting image, and the zeroed tail after them
-  STEP(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
+  // (with no iteration, c_proj is the starting image's copy)
+  STEP(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], n_iter == 0 ? c_proj : nullptr, cpy,
+                           cpx, st));
   STEP(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
     STEP(deam::launch_fill_u32(wmax, 0u, 16, st));
@@ -725,14 +728,15 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
     STEP(mark(k, 2));
     STEP(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
     STEP(mark(k, 3));
+    void* cp_out = k == n_iter - 1 ? c_proj : nullptr;   // the final iterate's copy
     if (pen) {
       double* cprev = (double*)(w + L.c_prev);
       STEP(hipMemcpyAsync(cprev, c64, (size_t)plan->gd.V * 2 * sizeof(double),
                           hipMemcpyDeviceToDevice, st));
       STEP(deam::launch_update_pen(plan, cprev, c64, w + L.b, Z[0], Z[1], pen->lambda,
-                                   pen->delta, nullptr, cpy, cpx, st));
+                                   pen->delta, cp_out, cpy, cpx, st));
     } else {
-      STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
+      STEP(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], cp_out, cpy, cpx, st));
     }
     STEP(mark(k, 4));
   }
@@ -760,10 +764,68 @@ static int iterate_impl(const deam_plan* plan, double* c64, const float* d, cons
   return ok();
 }
 
-int deam_iterate(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
-                 const double* Z, int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
-                 void* stream) {
-  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
+int deam_iterate(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                 const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                 void* ws, size_t ws_bytes, void* stream) {
+  return iterate_impl(plan, c64, c_proj, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream,
+                      nullptr);
+}
+
+int deam_iterate_sync(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                      const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (n_iter < 0) return fail(DEAM_ERR_VALUE, "n_iter must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  double* dev_hist = nullptr;
+  if (obj_hist && n_iter > 0) {
+    // the history is reduced on the device and copied out at the end
+    if (hipMalloc(&dev_hist, (size_t)n_iter * sizeof(double)) != hipSuccess)
+      return fail(DEAM_ERR_HIP, "hipMalloc of the objective history failed");
+  }
+  int rc = iterate_impl(plan, c64, c_proj, d, mask, Z, n_iter, dev_hist, ws, ws_bytes, stream,
+                        nullptr);
+  if (rc == DEAM_OK && dev_hist) {
+    const hipError_t e = hipMemcpyAsync(obj_hist, dev_hist, (size_t)n_iter * sizeof(double),
+                                        hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess)
+      rc = fail(DEAM_ERR_HIP, "copy of the objective history: %s", hipGetErrorString(e));
+  }
+  const std::string enqueue_err = rc == DEAM_OK ? std::string() : g_err;
+  // wait for the iterations, also after an enqueue error (earlier launches
+  // may be in flight), and report a device fault
+  const hipError_t es = hipStreamSynchronize(st);
+  if (dev_hist) (void)hipFree(dev_hist);
+  if (rc != DEAM_OK) {
+    g_err = enqueue_err;
+    return rc;
+  }
+  if (es != hipSuccess)
+    return fail(DEAM_ERR_HIP, "device fault during the iterations: %s", hipGetErrorString(es));
+  return ok();
+}
+
+int deam_validate_inputs(const deam_plan* plan, const double* c64, const float* d,
+                         int64_t* n_bad, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!ws) return fail(DEAM_ERR_NULL, "workspace is NULL");
+  if (ws_bytes < 16) return fail(DEAM_ERR_WORKSPACE, "workspace too small: %zu < 16 bytes", ws_bytes);
+  if (((uintptr_t)ws & 7) != 0) return fail(DEAM_ERR_VALUE, "workspace must be 8-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* cnt = (unsigned long long*)ws;
+  HIP_TRY(deam::launch_fill_u32((uint32_t*)cnt, 0u, 4, st));
+  HIP_TRY(deam::launch_validate(plan, c64, d, cnt, st));
+  unsigned long long h[2] = {0ull, 0ull};
+  HIP_TRY(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (n_bad) {
+    n_bad[0] = (int64_t)h[0];
+    n_bad[1] = (int64_t)h[1];
+  }
+  if (h[0] || h[1])
+    return fail(DEAM_ERR_VALUE, "%llu non-finite image values, %llu counts negative or non-finite",
+                h[0], h[1]);
+  return ok();
 }
 
 int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
@@ -771,8 +833,8 @@ int deam_iterate_penalized(const deam_plan* plan, double* c64, const float* d,
                            int32_t n_iter, double* obj_hist, void* ws, size_t ws_bytes,
                            void* stream) {
   const PenSpec pen{lambda, delta};
-  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr,
-                      &pen);
+  return iterate_impl(plan, c64, nullptr, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream,
+                      nullptr, &pen);
 }
 
 static int check_fbp(const deam_plan* plan) {
@@ -1045,14 +1107,16 @@ int deam_iterate_packed(const deam_plan* plan, double* c64, const float* d,
   if (!mask_bits) return fail(DEAM_ERR_NULL, "mask_bits is NULL");
   deam_plan q = *plan;   // the same plan reading the bit-packed trace
   q.gd.mbits = mask_bits;
-  return iterate_impl(&q, c64, d, nullptr, Z, n_iter, obj_hist, ws, ws_bytes, stream, nullptr);
+  return iterate_impl(&q, c64, nullptr, d, nullptr, Z, n_iter, obj_hist, ws, ws_bytes, stream,
+                      nullptr);
 }
 
-int deam_iterate_timed(const deam_plan* plan, double* c64, const float* d, const uint8_t* mask,
-                       const double* Z, int32_t n_iter, double* obj_hist, void* ws,
-                       size_t ws_bytes, void* stream, float* kernel_ms) {
+int deam_iterate_timed(const deam_plan* plan, double* c64, void* c_proj, const float* d,
+                       const uint8_t* mask, const double* Z, int32_t n_iter, double* obj_hist,
+                       void* ws, size_t ws_bytes, void* stream, float* kernel_ms) {
   if (!kernel_ms) return fail(DEAM_ERR_NULL, "kernel_ms is NULL");
-  return iterate_impl(plan, c64, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream, kernel_ms);
+  return iterate_impl(plan, c64, c_proj, d, mask, Z, n_iter, obj_hist, ws, ws_bytes, stream,
+                      kernel_ms);
 }
 
 }  // extern "C"

@@ -218,6 +218,10 @@ hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, ui
 hipError_t launch_pack_mask(const deam_plan* p, const uint8_t* mask, uint32_t* bits,
                             hipStream_t st);
 hipError_t launch_decompose(const deam_plan* p, const void* mu, double* c64, hipStream_t st);
+// input check: cnt[0] += non-finite entries of c64 [2][V], cnt[1] += entries
+// of d [2][R] that are negative or non-finite (either pointer may be NULL)
+hipError_t launch_validate(const deam_plan* p, const double* c64, const float* d,
+                           unsigned long long* cnt, hipStream_t st);
 
 WsLayout workspace_layout(const deam_plan* p, int op);
 

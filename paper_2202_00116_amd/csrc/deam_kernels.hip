@@ -2062,6 +2062,28 @@ __global__ __launch_bounds__(256) void k_pack_mask(int64_t R, const uint8_t* __r
   bits[i] = wv;
 }
 
+// Input check (a debug call, off the hot path): counts of non-finite image
+// values and of counts that are negative or non-finite.  Grid-stride loop,
+// one atomic per wave.
+__global__ __launch_bounds__(256) void k_validate(const double* __restrict__ c, int64_t nc,
+                                                  const float* __restrict__ d, int64_t nd,
+                                                  unsigned long long* __restrict__ cnt) {
+  unsigned long long bc = 0, bd = 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nc; i += stride)
+    bc += isfinite(c[i]) ? 0 : 1;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nd; i += stride)
+    bd += (isfinite(d[i]) && d[i] >= 0.f) ? 0 : 1;
+  for (int o = 32; o > 0; o >>= 1) {
+    bc += __shfl_down(bc, o);
+    bd += __shfl_down(bd, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (bc) atomicAdd(&cnt[0], bc);
+    if (bd) atomicAdd(&cnt[1], bd);
+  }
+}
+
 inline dim3 image_grid(const deam_plan* p) {
   return dim3((p->gd.nx + 31) / 32, (p->gd.ny + 31) / 32, p->gd.is3d ? p->gd.nz : 1);
 }
@@ -2451,6 +2473,17 @@ hipError_t launch_dilate(const deam_plan* p, const uint8_t* mask, int radius, ui
   const int64_t R = p->gd.R;
   hipLaunchKernelGGL(k_dilate, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, R,
                      p->gd.n_cols, radius, mask, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const deam_plan* p, const double* c64, const float* d,
+                           unsigned long long* cnt, hipStream_t st) {
+  const int64_t nc = c64 ? 2 * p->gd.V : 0, nd = d ? 2 * p->gd.R : 0;
+  const int64_t n = max(nc, nd);
+  const int64_t nb = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(nb < 4096 ? nb : 4096);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, st, c64, nc, d, nd, cnt);
   return hipGetLastError();
 }
 

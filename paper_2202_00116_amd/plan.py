@@ -128,13 +128,16 @@ class Plan:
                                         _ptr(w), _ptr(g), _ptr(obj), ws, n, _stream()))
         return w, g, obj
 
-    def backproject(self, w):
-        """b[c] = H^T w[c] for w of shape (n_ch, R), n_ch in {1, 2, 4}."""
+    def backproject(self, w, nonneg=False):
+        """b[c] = H^T w[c] for w of shape (n_ch, R), n_ch in {1, 2, 4}.
+        nonneg=True promises w >= 0 everywhere (the AM weights): the
+        accumulation deam_iterate uses (packed for 4 channels of a mixed plan)."""
         n_ch = w.shape[0]
         self._check(w, (n_ch, self.R), self.dtype, "w")
         b = torch.empty((n_ch, self.V), dtype=self.dtype, device=self.device)
         ws, n = self.workspace(L.OP_BACKPROJECT)
-        L.check(self.lib.deam_backproject(self._p, _ptr(w), n_ch, _ptr(b), ws, n, _stream()))
+        L.check(self.lib.deam_backproject(self._p, _ptr(w), n_ch, L.BP_NONNEG if nonneg else 0,
+                                          _ptr(b), ws, n, _stream()))
         return b
 
     def update(self, c64, b, Z, want_proj=False):
@@ -147,19 +150,51 @@ class Plan:
                                      Zh.ctypes.data_as(C.c_void_p), _stream()))
         return cp
 
-    def iterate(self, c64, d, mask, Z, n_iter, obj_hist=None):
+    def iterate(self, c64, d, mask, Z, n_iter, obj_hist=None, c_proj=None):
         """n_iter DEAM iterations in place on c64; obj_hist (device float64 [n_iter])
-        receives the masked I-divergence at each iterate."""
+        receives the masked I-divergence at each iterate, c_proj ([2, V] in the
+        plan precision) the final iterate's copy."""
         self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(c_proj, (2, self.V), self.dtype, "c_proj")
         self._check(d, (2, self.R), torch.float32, "d")
         self._check(mask, (self.R,), torch.uint8, "mask")
         self._check(obj_hist, (n_iter,), torch.float64, "obj_hist")
         Zh = np.ascontiguousarray(Z, dtype=np.float64)
         ws, n = self.workspace(L.OP_ITERATE)
-        L.check(self.lib.deam_iterate(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+        L.check(self.lib.deam_iterate(self._p, _ptr(c64), _ptr(c_proj), _ptr(d), _ptr(mask),
                                       Zh.ctypes.data_as(C.c_void_p), int(n_iter), _ptr(obj_hist),
                                       ws, n, _stream()))
         return c64
+
+    def iterate_sync(self, c64, d, mask, Z, n_iter, c_proj=None):
+        """iterate() that waits for the device and returns the objective history
+        as a host float64 array (deam_iterate_sync: a device fault raises)."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(c_proj, (2, self.V), self.dtype, "c_proj")
+        self._check(d, (2, self.R), torch.float32, "d")
+        self._check(mask, (self.R,), torch.uint8, "mask")
+        Zh = np.ascontiguousarray(Z, dtype=np.float64)
+        hist = np.zeros(max(int(n_iter), 0))
+        ws, n = self.workspace(L.OP_ITERATE)
+        L.check(self.lib.deam_iterate_sync(self._p, _ptr(c64), _ptr(c_proj), _ptr(d), _ptr(mask),
+                                           Zh.ctypes.data_as(C.c_void_p), int(n_iter),
+                                           hist.ctypes.data_as(C.c_void_p), ws, n, _stream()))
+        return hist
+
+    def validate_inputs(self, c64=None, d=None):
+        """Debug check (synchronous): c64 finite, d finite and >= 0.  Returns
+        the numbers of offending entries; raises DeamError when any is found."""
+        self._check(c64, (2, self.V), torch.float64, "c64")
+        self._check(d, (2, self.R), torch.float32, "d")
+        ws, n = self.workspace(L.OP_BACKPROJECT)
+        bad = (C.c_int64 * 2)()
+        rc = self.lib.deam_validate_inputs(self._p, _ptr(c64), _ptr(d), bad, ws, n, _stream())
+        if rc not in (0, -7):
+            L.check(rc)
+        counts = (bad[0], bad[1])
+        if rc == -7:
+            L.check(rc)
+        return counts
 
     def penalty(self, c64, lam, delta):
         """R(c) of Eq. 6 (fair potential, 1/distance neighbourhood) as a
@@ -313,7 +348,7 @@ class Plan:
         Zh = np.ascontiguousarray(Z, dtype=np.float64)
         ws, n = self.workspace(L.OP_ITERATE)
         ms = (C.c_float * 4)()
-        L.check(self.lib.deam_iterate_timed(self._p, _ptr(c64), _ptr(d), _ptr(mask),
+        L.check(self.lib.deam_iterate_timed(self._p, _ptr(c64), None, _ptr(d), _ptr(mask),
                                             Zh.ctypes.data_as(C.c_void_p), int(n_iter),
                                             _ptr(obj_hist), ws, n, _stream(), ms))
         return dict(fp_poly=ms[0], backproject=ms[1], update=ms[2], loop=ms[3])

@@ -86,8 +86,10 @@ def test_null_plan_calls(lib):
     assert lib.deam_workspace_size(None, 0, C.byref(n)) == -1
     assert lib.deam_plan_destroy(None) == -1
     assert lib.deam_forward(None, None, 2, None, None, 0, None) == -1
-    assert lib.deam_backproject(None, None, 4, None, None, 0, None) == -1
-    assert lib.deam_iterate(None, None, None, None, None, 1, None, None, 0, None) == -1
+    assert lib.deam_backproject(None, None, 4, 0, None, None, 0, None) == -1
+    assert lib.deam_iterate(None, None, None, None, None, None, 1, None, None, 0, None) == -1
+    assert lib.deam_iterate_sync(None, None, None, None, None, None, 1, None, None, 0, None) == -1
+    assert lib.deam_validate_inputs(None, None, None, None, None, 0, None) == -1
     assert lib.deam_update(None, None, None, None, None, None) == -1
     assert lib.deam_poly_mean(None, None, None, None, 0, None, None, None, None, None, 0, None) == -1
     assert lib.deam_metal_trace(None, None, 0.5, None, None, None, 0, None) == -1

@@ -106,3 +106,50 @@ def test_dilate_rejects_overlap_and_radius(setup):
         plan.dilate_mask(m, plan.geom.n_cols + 1)
     rc = plan.lib.deam_dilate_mask(plan._p, _vp(m), 1, C.c_void_p(m.data_ptr() + 1), None)
     assert rc == -7
+
+
+def test_iterate_c_proj_and_host_history(setup):
+    """deam_iterate's c_proj is the final iterate in the plan precision (also
+    with zero iterations), and deam_iterate_sync returns the same history in
+    host memory, bit for bit, after waiting for the device."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = setup[0]
+    d = torch.tensor(inp["d"], device=DEV)
+    for prec in ("mixed", "fp64"):
+        plan = Plan(inp["geom"], inp["I0"], inp["mu"], prec)
+        c_a = torch.tensor(inp["c0"], device=DEV)
+        cp = torch.full((2, plan.V), float("nan"), dtype=plan.dtype, device=DEV)
+        h_a = torch.zeros(3, dtype=torch.float64, device=DEV)
+        plan.iterate(c_a, d, None, inp["Z"], 3, h_a, c_proj=cp)
+        assert torch.equal(cp, c_a.to(plan.dtype))
+        c_b = torch.tensor(inp["c0"], device=DEV)
+        cp_b = torch.empty_like(cp)
+        h_b = plan.iterate_sync(c_b, d, None, inp["Z"], 3, c_proj=cp_b)
+        assert torch.equal(c_a, c_b) and torch.equal(cp, cp_b)
+        assert np.array_equal(h_a.cpu().numpy(), h_b)
+        c0 = torch.tensor(inp["c0"], device=DEV)
+        cp0 = torch.full_like(cp, float("nan"))
+        assert plan.iterate_sync(c0, d, None, inp["Z"], 0, c_proj=cp0).size == 0
+        assert torch.equal(cp0, c0.to(plan.dtype))
+
+
+def test_validate_inputs(setup):
+    from paper_2202_00116_amd._lib import DeamError
+    inp, plan = setup
+    c = torch.tensor(inp["c0"], device=DEV)
+    d = torch.tensor(inp["d"], device=DEV)
+    assert plan.validate_inputs(c, d) == (0, 0)
+    assert plan.validate_inputs(None, d) == (0, 0)
+    c[1, 17] = float("nan")
+    c[0, 3] = float("inf")
+    d[0, 5] = -1.0
+    d[1, 9] = float("nan")
+    d[1, 11] = -0.0          # -0 is a valid count
+    with pytest.raises(DeamError, match="VALUE"):
+        plan.validate_inputs(c, d)
+    bad = (C.c_int64 * 2)()
+    ws, n = plan.workspace(2)
+    rc = plan.lib.deam_validate_inputs(plan._p, _vp(c), _vp(d), bad, ws, n, None)
+    assert rc == -7 and (bad[0], bad[1]) == (2, 2)
+    assert b"non-finite" in plan.lib.deam_last_error()
+    assert plan.lib.deam_validate_inputs(plan._p, _vp(c), _vp(d), bad, ws, C.c_size_t(8), None) == -4

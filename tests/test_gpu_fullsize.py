@@ -2,22 +2,25 @@
 
 fan512 (2D, 512^2, 984 x 816 rays): the oracle runs the whole problem: metal
 mask (bit-exact), forward projection, backprojection, two full DEAM iterations
-and the 20 iterations of the stated image tolerance.  helical (512^2 x 64, 4608 x 16 x 816 rays): the oracle computes
-sampled rays one by one (line integrals, metal trace, expected counts);
-properties that hold at any size (adjoint identity, monotone objective) cover
-the rest."""
+and the 20 iterations of the stated image tolerance.
+helical (512^2 x 64, 4608 x 16 x 816 = 60 M rays, 36 backprojector view
+batches): the oracle runs the whole problem too, on all host cores: the metal
+mask over every ray (bit-exact) and two DEAM iterations over the whole volume
+in both precisions (image and objective); sampled rays (line integrals,
+expected counts, weights) and properties that hold at any size (adjoint
+identity, monotone objective) add to that.  Each oracle stage takes one to
+two minutes on 16 cores and runs in the first test that needs it."""
+import time
+
 import numpy as np
 import pytest
 import torch
 
 from workloads import make_inputs
+from tests.errors import assert_close
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 DEV = "cuda"
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) / np.linalg.norm(np.asarray(b, float)))
 
 
 @pytest.fixture(scope="module")
@@ -44,22 +47,19 @@ def test_fan512_full(orc, fan512):
     c32 = inp["c0"].astype(np.float32).astype(np.float64)
     l_o = orc.forward(g, c32)
     l = plan.forward(torch.tensor(c32, dtype=torch.float32, device=DEV)).cpu().numpy()
-    print("fan512 forward rel", rel(l, l_o))
-    assert rel(l, l_o) <= 1e-5
+    assert_close(l, l_o, 1e-5, what="fan512 forward")
     # backprojection of non-negative weights
     rng = np.random.default_rng(21)
     w = rng.uniform(0, 1, (4, g.n_rays)).astype(np.float32).astype(np.float64)
     b_o = orc.backproject(g, w)
     b = plan.backproject(torch.tensor(w, dtype=torch.float32, device=DEV)).cpu().numpy()
-    print("fan512 backproject rel", rel(b, b_o))
-    assert rel(b, b_o) <= 1e-5
+    assert_close(b, b_o, 1e-5, what="fan512 backproject")
     # two DEAM iterations from the cold start, with the objective history
     c_o, h_o = orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], inp["c0"], 2)
     c = torch.tensor(inp["c0"], device=DEV)
     hist = torch.zeros(2, dtype=torch.float64, device=DEV)
     plan.iterate(c, torch.tensor(inp["d"], device=DEV), mask, inp["Z"], 2, hist)
-    print("fan512 2-iteration image rel", rel(c.cpu().numpy(), c_o))
-    assert rel(c.cpu().numpy(), c_o) <= 1e-5
+    assert_close(c.cpu().numpy(), c_o, 1e-5, what="fan512 image after 2 iterations")
     assert np.abs(hist.cpu().numpy() - h_o).max() <= 1e-6 * h_o[0]
 
 
@@ -80,10 +80,10 @@ def test_fan512_20_iterations_against_oracle(orc, fan512):
         c = torch.tensor(inp["c0"], device=DEV)
         hist = torch.zeros(n, dtype=torch.float64, device=DEV)
         plan.iterate(c, d, mask, inp["Z"], n, hist)
-        e = rel(c.cpu().numpy(), c_o)
         eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
-        print(f"fan512 {prec} 20 iterations: image rel {e:.3e}, objective rel {eh:.3e}")
-        assert e <= tol and eh <= htol
+        print(f"fan512 {prec} 20 iterations: objective rel {eh:.3e}")
+        assert_close(c.cpu().numpy(), c_o, tol, what=f"fan512 {prec} image after 20 iterations")
+        assert eh <= htol
 
 
 def test_fan512_objective_monotone_50_iterations(fan512):
@@ -114,8 +114,7 @@ def test_fan512_mixed_tracks_fp64_over_50_iterations(fan512):
         c = torch.tensor(inp["c0"], device=DEV)
         plan.iterate(c, d, mask, inp["Z"], 50)
         out[prec] = c.cpu().numpy()
-    print("fan512 50 iterations mixed vs fp64", rel(out["mixed"], out["fp64"]))
-    assert rel(out["mixed"], out["fp64"]) <= 1e-4
+    assert_close(out["mixed"], out["fp64"], 1e-4, what="fan512 50 iterations mixed vs fp64")
 
 
 def test_helical_sampled(orc, helical):
@@ -136,16 +135,15 @@ def test_helical_sampled(orc, helical):
     c = rng.uniform(0, 1, (2, g.n_voxels)).astype(np.float32)
     l = plan.forward(torch.tensor(c, device=DEV))[:, rays_t].cpu().numpy()
     l_o = orc.forward_rays(g, c.astype(np.float64), rays)
-    print("helical sampled forward rel", rel(l, l_o))
-    assert rel(l, l_o) <= 1e-5
+    assert_close(l, l_o, 1e-5, what="helical sampled forward")
     # expected counts and weights on the sampled rays, from the GPU's line integrals
     lt = plan.forward(torch.tensor(inp["c0"], dtype=torch.float32, device=DEV))
     d = torch.tensor(inp["d"], device=DEV)
     w, gg, _ = plan.poly_mean(lt, d, mask, want_g=True)
     w_o, g_o, _ = orc.poly_mean(inp["I0"], inp["mu"], lt[:, rays_t].double().cpu().numpy(),
                                 inp["d"][:, rays], mask[rays_t].cpu().numpy())
-    assert rel(gg[:, rays_t].cpu().numpy(), g_o) <= 1e-5
-    assert rel(w[:, rays_t].cpu().numpy(), w_o) <= 1e-5
+    assert_close(gg[:, rays_t].cpu().numpy(), g_o, 1e-5, what="helical sampled g")
+    assert_close(w[:, rays_t].cpu().numpy(), w_o, 1e-5, what="helical sampled weights")
 
 
 def test_helical_adjoint_and_monotone(helical):
@@ -181,3 +179,73 @@ def test_helical_adjoint_and_monotone(helical):
     plan.iterate(c, torch.tensor(inp["d"], device=DEV), mask, inp["Z"], 4, hist)
     h = hist.cpu().numpy()
     assert np.all(np.diff(h) <= 1e-7 * h[:-1]), h
+
+
+@pytest.fixture(scope="module")
+def helical_trace(orc, helical):
+    inp = helical
+    t0 = time.time()
+    mask_o, T_o = orc.metal_trace(inp["geom"], inp["metal"], inp["t"])
+    print(f"oracle helical metal trace: {time.time() - t0:.1f} s on {orc.num_threads()} threads",
+          flush=True)
+    return mask_o, T_o
+
+
+def test_helical_mask_all_rays(helical, helical_trace):
+    """The metal mask over all 60 162 048 rays, bit for bit (FP64 trace on
+    both sides), with the trace itself to 1e-9 mm."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = helical
+    mask_o, T_o = helical_trace
+    plan = Plan(inp["geom"], inp["I0"], inp["mu"], "mixed")
+    mask, T = plan.metal_trace(torch.tensor(inp["metal"], device=DEV), inp["t"], want_T=True)
+    T = T.cpu().numpy()
+    print("helical trace: metal rays", int(mask_o.sum()), "margin", float(np.abs(T_o - inp["t"]).min()),
+          "max |T - T_o|", float(np.abs(T - T_o).max()))
+    assert np.array_equal(mask.cpu().numpy(), mask_o)
+    assert np.abs(T - T_o).max() < 1e-9
+    assert mask_o.sum() > 0
+
+
+@pytest.fixture(scope="module")
+def helical_oracle_iterates(helical):
+    """The oracle's iterates c^0, c^1, ... and objectives F(c^0), ..., grown on
+    demand one iteration at a time (an iteration is deterministic, so
+    iterating from c^k once gives c^(k+1))."""
+    return {"c": [helical["c0"]], "h": []}
+
+
+def oracle_iterate_to(orc, inp, mask_o, state, k):
+    while len(state["c"]) <= k:
+        t0 = time.time()
+        c, h = orc.iterate(inp["geom"], inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"],
+                           state["c"][-1], 1)
+        state["c"].append(c)
+        state["h"].append(float(h[0]))
+        print(f"oracle helical iteration {len(state['c']) - 1}: {time.time() - t0:.1f} s", flush=True)
+    return state["c"][k], np.array(state["h"][:k])
+
+
+@pytest.mark.parametrize("k,prec,tol,htol", [(1, "mixed", 1e-5, 1e-6), (1, "fp64", 1e-10, 1e-10),
+                                             (2, "mixed", 1e-5, 1e-6), (2, "fp64", 1e-10, 1e-10)])
+def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_oracle_iterates,
+                                         k, prec, tol, htol):
+    """k DEAM iterations of the whole helical workload (the fused 3D projector,
+    the packed backprojection over all 36 view batches, the FP64 update)
+    against the oracle over the whole volume: the image c^k and the
+    objectives F(c^0), ..., F(c^(k-1))."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = helical
+    mask_o, _ = helical_trace
+    c_o, h_o = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, k)
+    plan = Plan(inp["geom"], inp["I0"], inp["mu"], prec)
+    c = torch.tensor(inp["c0"], device=DEV)
+    hist = torch.zeros(k, dtype=torch.float64, device=DEV)
+    plan.iterate(c, torch.tensor(inp["d"], device=DEV), torch.tensor(mask_o, device=DEV),
+                 inp["Z"], k, hist)
+    eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
+    print(f"helical {prec} after {k} iterations: objective rel {eh:.3e}")
+    assert_close(c.cpu().numpy(), c_o, tol, what=f"helical {prec} image after {k} iterations")
+    assert eh <= htol
+    del plan
+    torch.cuda.empty_cache()

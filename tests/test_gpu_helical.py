@@ -1,0 +1,140 @@
+"""Helical parity beyond one backprojector view batch.
+
+The backprojector works through the views in batches of 128, and for the
+four non-negative DEAM weights of a mixed plan it packs two channels into one
+fixed-point LDS word with a per-batch scale and moves every batch into 64-bit
+totals.  These tests run that path over many batches against the FP64
+oracle: a mid-size helix (96^2 x 24, 8 rows, 640 views over two turns, five
+batches) for the workload's 20 iterations, seeded random helices with 300 to
+600 views, and the weakest voxels of the packed backprojection, where the
+fixed-point resolution is coarsest relative to the value."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import make_inputs
+from workloads import geometry as G
+from tests.errors import assert_close, rel_max
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return make_inputs("helical_mid")
+
+
+@pytest.fixture(scope="module")
+def mid_oracle(orc, mid):
+    inp = mid
+    g = inp["geom"]
+    mask_o, _ = orc.metal_trace(g, inp["metal"], inp["t"])
+    c_o, h_o = orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], inp["c0"],
+                           inp["n_iter"])
+    return mask_o, c_o, h_o
+
+
+@pytest.mark.parametrize("prec,tol,htol", [("mixed", 1e-4, 1e-5), ("fp64", 1e-10, 1e-10)])
+def test_helical_mid_20_iterations(mid, mid_oracle, prec, tol, htol):
+    from paper_2202_00116_amd.plan import Plan
+    inp = mid
+    g = inp["geom"]
+    mask_o, c_o, h_o = mid_oracle
+    plan = Plan(g, inp["I0"], inp["mu"], prec)
+    mask = plan.metal_trace(torch.tensor(inp["metal"], device=DEV), inp["t"])
+    assert np.array_equal(mask.cpu().numpy(), mask_o)
+    assert mask_o.sum() > 0
+    n = inp["n_iter"]
+    c = torch.tensor(inp["c0"], device=DEV)
+    hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+    plan.iterate(c, torch.tensor(inp["d"], device=DEV), mask, inp["Z"], n, hist)
+    eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
+    print(f"helical_mid {prec}: objective history rel {eh:.3e}")
+    assert_close(c.cpu().numpy(), c_o, tol, what=f"helical_mid {prec} image after {n} iterations")
+    assert eh <= htol
+    assert np.all(np.diff(h_o) < 0)
+
+
+def random_long_helix(seed):
+    """A seeded helical scan with 300 to 600 views (three to five batches of
+    the backprojector), 1 to 9 rows, grids of 8 to 48 pixels a side and 2 to
+    14 slices, one to three turns, and a feed of up to a collimation per turn."""
+    r = np.random.default_rng(seed)
+    nx, ny, nz = int(r.integers(8, 49)), int(r.integers(8, 49)), int(r.integers(2, 15))
+    dx, dy, dz = float(r.uniform(0.6, 1.4)), float(r.uniform(0.6, 1.4)), float(r.uniform(0.6, 1.6))
+    n_rows, n_cols = int(r.integers(1, 10)), int(r.integers(16, 120))
+    n_views = int(r.integers(300, 601))
+    rad = 0.5 * np.hypot(nx * dx, ny * dy)
+    sid = float(r.uniform(1.5, 6.0)) * rad
+    sdd = sid + rad * float(r.uniform(1.1, 3.0))
+    drow = float(r.uniform(0.5, 2.0))
+    vpr = float(n_views) / float(r.uniform(1.0, 3.0))
+    feed = float(r.uniform(0.2, 1.0)) * n_rows * drow
+    return G.Geometry(kind=1, nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, n_views=n_views,
+                      n_rows=n_rows, n_cols=n_cols, sid=sid, sdd=sdd,
+                      dgamma=G.fan_dgamma(nx, ny, dx, dy, sid, n_cols) * float(r.uniform(0.9, 1.2)),
+                      col_offset=float(r.uniform(-0.5, 0.5)), drow_iso=drow,
+                      beta0=float(r.uniform(0, 2 * np.pi)), views_per_rot=vpr, feed_per_rot=feed)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_random_long_helices_iterate(orc, prec, tol):
+    """Three DEAM iterations on six seeded random helices of 300-600 views
+    (the packed backprojection over several batches), data from the spine
+    phantom scaled to the grid, against the oracle."""
+    from paper_2202_00116_amd.plan import Plan
+    from workloads.configs import cold_start, expected_counts, surrogate_Z, spine_phantom
+    from workloads.phantoms import metal_fraction
+    from workloads.physics import basis_mu, spectra as make_spectra
+    I0, mu = make_spectra(1e5), basis_mu()
+    for seed in range(400, 406):
+        g = random_long_helix(seed)
+        zhalf = 0.5 * g.nz * g.dz
+        ph = spine_phantom(0.45 * min(g.nx * g.dx, g.ny * g.dy) / 180.0, zhalf, 0.4 * zhalf)
+        d = np.random.default_rng(seed).poisson(expected_counts(g, ph, I0)).astype(np.float32)
+        metal = (metal_fraction(ph, g, 2) >= 0.5).astype(np.uint8).reshape(-1)
+        mask_o, _ = orc.metal_trace(g, metal, 0.5 * min(g.dx, g.dy))
+        c0, Z, n = cold_start(g, I0), surrogate_Z(g, mu, I0), 3
+        c_o, h_o = orc.iterate(g, I0, mu, d, mask_o, Z, c0, n)
+        plan = Plan(g, I0, mu, prec)
+        c = torch.tensor(c0, device=DEV)
+        hist = torch.zeros(n, dtype=torch.float64, device=DEV)
+        plan.iterate(c, torch.tensor(d, device=DEV), torch.tensor(mask_o, device=DEV), Z, n, hist)
+        eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
+        tag = (f"seed {seed} {g.nx}x{g.ny}x{g.nz} {g.n_views}x{g.n_rows}x{g.n_cols} {prec} "
+               f"trace rays {int(mask_o.sum())}")
+        print(f"{tag}: objective {eh:.2e}")
+        assert_close(c.cpu().numpy(), c_o, tol, what=tag + " image")
+        assert eh <= (1e-5 if prec == "mixed" else 1e-9), seed
+
+
+@pytest.mark.parametrize("name", ["fan512", "helical_mid"])
+def test_packed_backprojection_weakest_voxels(orc, name):
+    """b~ and b^ from the accumulation deam_iterate uses (packed, non-negative,
+    four channels), on the DEAM weights at the cold start, against the
+    oracle: over the whole image and on the 1 % of seen voxels with the
+    smallest backprojections, element by element relative to each voxel's own
+    value (the fixed-point resolution is set by the largest weight of a view
+    batch, so it is coarsest there)."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = make_inputs(name)
+    g = inp["geom"]
+    mask_o, _ = orc.metal_trace(g, inp["metal"], inp["t"])
+    plan = Plan(g, inp["I0"], inp["mu"], "mixed")
+    l = plan.forward(torch.tensor(inp["c0"], dtype=torch.float32, device=DEV))
+    w, _, _ = plan.poly_mean(l, torch.tensor(inp["d"], device=DEV), torch.tensor(mask_o, device=DEV))
+    b = plan.backproject(w, nonneg=True).cpu().numpy()
+    b_o = orc.backproject(g, w.double().cpu().numpy())
+    assert_close(b, b_o, 1e-5, what=f"{name} packed backprojection")
+    worst = 0.0
+    for ch in range(4):
+        seen = np.nonzero(b_o[ch] > 0)[0]
+        k = max(1, seen.size // 100)
+        weak = seen[np.argsort(b_o[ch][seen])[:k]]
+        e = np.abs(b[ch][weak] - b_o[ch][weak]) / b_o[ch][weak]
+        print(f"{name} channel {ch}: weakest 1% ({k} voxels, b_o {b_o[ch][weak].min():.3e}.."
+              f"{b_o[ch][weak].max():.3e}, max b_o {b_o[ch].max():.3e}): max rel {e.max():.3e}, "
+              f"median {np.median(e):.3e}")
+        worst = max(worst, float(e.max()))
+    assert worst <= 1e-3, worst

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from workloads import make_inputs
+from tests.errors import rel_l2, rel_max
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -18,7 +19,9 @@ def _plan(inp, prec):
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+    """The larger of the relative L2 error and the element-wise error (max-abs
+    relative to max |b|): a bound on it bounds both."""
+    return max(rel_l2(a, b), rel_max(a, b))
 
 
 @pytest.mark.parametrize("name,n_sub,n_iter", [("fan64", 4, 5), ("fan64", 5, 3),

@@ -1,5 +1,6 @@
 """GPU parity: every C-ABI call against the FP64 CPU oracle on the same seeded
-inputs.  Tolerances (relative L2 over the whole result unless stated):
+inputs.  Each result is checked twice (tests/errors.py): relative L2 over the
+whole array, and element-wise, max |x - x_o| relative to max |x_o|.  Bounds:
   mixed precision: projections, g and weights <= 1e-5; images after 20
                    iterations <= 1e-4; masks bit-exact;
   fp64:            <= 1e-10 (projections, weights, images).
@@ -10,15 +11,11 @@ import torch
 
 from workloads import make_inputs, geometry_for
 from workloads import geometry as G
+from tests.errors import rel_l2 as rel, rel_max, assert_close
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
-
-
-def rel(a, b):
-    a, b = np.asarray(a, float), np.asarray(b, float)
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
 def odd_fan():
@@ -92,10 +89,9 @@ def test_forward(orc, spectra, gname, prec, tol):
     l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
     # the oracle is fed the values the GPU sees (rounded to the plan precision)
     ref = orc.forward(g, c.astype(np.float32).astype(np.float64)) if prec == "mixed" else ref
-    print(gname, prec, "forward rel", rel(l, ref))
-    assert rel(l, ref) <= tol
+    assert_close(l, ref, tol, what=f"{gname} {prec} forward")
     l1 = plan.forward(torch.tensor(c[:1], dtype=plan.dtype, device=DEV)).cpu().numpy()
-    assert rel(l1, ref[:1]) <= tol
+    assert_close(l1, ref[:1], tol, what=f"{gname} {prec} forward 1 ch")
 
 
 @pytest.mark.parametrize("gname", list(GEOMS))
@@ -111,8 +107,7 @@ def test_backproject(orc, spectra, gname, prec, tol, nch):
         w = w.astype(np.float32).astype(np.float64)
     ref = orc.backproject(g, w)
     b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
-    print(gname, prec, nch, "backproject rel", rel(b, ref))
-    assert rel(b, ref) <= tol
+    assert_close(b, ref, tol, what=f"{gname} {prec} {nch} ch backproject")
     # signed weights: the sums cancel, so the error is measured against H^T |w|
     ws = rng.standard_normal((nch, g.n_rays))
     if prec == "mixed":
@@ -120,8 +115,11 @@ def test_backproject(orc, spectra, gname, prec, tol, nch):
     ref = orc.backproject(g, ws)
     scale = np.linalg.norm(orc.backproject(g, np.abs(ws)))
     b = plan.backproject(torch.tensor(ws, dtype=plan.dtype, device=DEV)).cpu().numpy()
-    print(gname, prec, nch, "signed backproject err / |H^T|w||", np.linalg.norm(b - ref) / scale)
+    smax = np.abs(orc.backproject(g, np.abs(ws))).max()
+    print(gname, prec, nch, "signed backproject err / |H^T|w||", np.linalg.norm(b - ref) / scale,
+          "max err / max H^T|w|", np.abs(b - ref).max() / smax)
     assert np.linalg.norm(b - ref) <= tol * scale
+    assert np.abs(b - ref).max() <= tol * smax
 
 
 @pytest.mark.parametrize("gname", ["fan64", "helical_small", "odd_helix"])
@@ -152,8 +150,19 @@ def test_poly_mean(orc, prec, tol, mode):
                                 torch.tensor(inp["d"], device=DEV),
                                 torch.tensor(mask, device=DEV), mode=mode, want_g=True,
                                 want_obj=True)
-    assert rel(gg.cpu().numpy(), g_o) <= tol
-    assert rel(w.cpu().numpy(), w_o) <= tol * (10 if mode == 1 else 1)
+    assert_close(gg.cpu().numpy(), g_o, tol, what=f"{prec} mode {mode} g")
+    if mode == 1:
+        # u_i = sum_j (d_j/g_j - 1) a_ij cancels where d ~ g (Poisson noise of
+        # a few 1e-3), so the relative L2 bound is 10 tol, and the element-wise
+        # error is measured against the scale of its terms, sum_j (d_j/g_j + 1) a_ij
+        w_np = w.cpu().numpy()
+        wa, _, _ = orc.poly_mean(inp["I0"], inp["mu"], l, inp["d"], mask, mode=0)
+        scale = wa[:2] + wa[2:]
+        em = np.abs(w_np - w_o).max() / np.abs(scale).max()
+        print(prec, "GRAD weights rel L2", rel(w_np, w_o), "max err / max scale", em)
+        assert rel(w_np, w_o) <= 10 * tol and em <= tol
+    else:
+        assert_close(w.cpu().numpy(), w_o, tol, what=f"{prec} mode {mode} weights")
     assert abs(obj.item() - obj_o.sum()) <= (1e-6 if prec == "mixed" else 1e-10) * abs(obj_o.sum())
 
 
@@ -186,8 +195,8 @@ def test_iterate(orc, name, n, prec, tol):
                  inp["Z"], n, hist)
     c = c.cpu().numpy()
     h = hist.cpu().numpy()
-    print(name, prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
-    assert rel(c, c_o) <= tol
+    print(name, prec, "hist rel", np.abs(h - h_o).max() / h_o[0])
+    assert_close(c, c_o, tol, what=f"{name} {prec} image after {n} iterations")
     assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
 
 
@@ -212,8 +221,8 @@ def test_iterate_wide_fan(orc, prec, tol):
     hist = torch.zeros(n, dtype=torch.float64, device=DEV)
     plan.iterate(c, torch.tensor(d, device=DEV), torch.tensor(mask_o, device=DEV), Z, n, hist)
     c, h = c.cpu().numpy(), hist.cpu().numpy()
-    print("wide_fan", prec, "image rel", rel(c, c_o), "hist rel", np.abs(h - h_o).max() / h_o[0])
-    assert rel(c, c_o) <= tol
+    print("wide_fan", prec, "hist rel", np.abs(h - h_o).max() / h_o[0])
+    assert_close(c, c_o, tol, what=f"wide_fan {prec} image")
     assert np.abs(h - h_o).max() <= (1e-5 if prec == "mixed" else 1e-9) * h_o[0]
 
 
@@ -236,7 +245,7 @@ def test_degenerate_rays(orc, spectra, prec, tol):
     if prec == "mixed":
         img = img.astype(np.float32).astype(np.float64)
     l = plan.forward(torch.tensor(img, dtype=plan.dtype, device=DEV)).cpu().numpy()
-    assert rel(l, orc.forward(g, img)) <= tol
+    assert_close(l, orc.forward(g, img), tol, what=f"axis_fan {prec} forward")
     w = rng.uniform(0, 1, (1, g.n_rays))
     if prec == "mixed":
         w = w.astype(np.float32).astype(np.float64)
@@ -300,9 +309,9 @@ def test_random_fans(orc, spectra, prec, tol):
             w = w.astype(np.float32).astype(np.float64)
         l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
         b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
-        el, eb = rel(l, orc.forward(g, c)), rel(b, orc.backproject(g, w))
-        print(f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}: forward {el:.2e}, backproject {eb:.2e}")
-        assert el <= tol and eb <= tol, seed
+        tag = f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}"
+        assert_close(l, orc.forward(g, c), tol, what=tag + " forward")
+        assert_close(b, orc.backproject(g, w), tol, what=tag + " backproject")
 
 
 @pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
@@ -326,11 +335,11 @@ def test_random_fans_iterate(orc, prec, tol):
         c = torch.tensor(c0, device=DEV)
         hist = torch.zeros(n, dtype=torch.float64, device=DEV)
         plan.iterate(c, torch.tensor(d, device=DEV), torch.tensor(mask_o, device=DEV), Z, n, hist)
-        e = rel(c.cpu().numpy(), c_o)
         eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
-        print(f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}: image {e:.2e}, "
-              f"objective {eh:.2e}, trace rays {int(mask_o.sum())}")
-        assert e <= tol and eh <= (1e-5 if prec == "mixed" else 1e-9), seed
+        tag = f"seed {seed} {g.nx}x{g.ny} {g.n_views}x{g.n_cols} {prec}"
+        print(f"{tag}: objective {eh:.2e}, trace rays {int(mask_o.sum())}")
+        assert_close(c.cpu().numpy(), c_o, tol, what=tag + " image")
+        assert eh <= (1e-5 if prec == "mixed" else 1e-9), seed
 
 
 def random_helix(seed):
@@ -370,10 +379,9 @@ def test_random_helices(orc, spectra, prec, tol):
             w = w.astype(np.float32).astype(np.float64)
         l = plan.forward(torch.tensor(c, dtype=plan.dtype, device=DEV)).cpu().numpy()
         b = plan.backproject(torch.tensor(w, dtype=plan.dtype, device=DEV)).cpu().numpy()
-        el, eb = rel(l, orc.forward(g, c)), rel(b, orc.backproject(g, w))
-        print(f"seed {seed} {g.nx}x{g.ny}x{g.nz} {g.n_views}x{g.n_rows}x{g.n_cols} {prec}: "
-              f"forward {el:.2e}, backproject {eb:.2e}")
-        assert el <= tol and eb <= tol, seed
+        tag = f"seed {seed} {g.nx}x{g.ny}x{g.nz} {g.n_views}x{g.n_rows}x{g.n_cols} {prec}"
+        assert_close(l, orc.forward(g, c), tol, what=tag + " forward")
+        assert_close(b, orc.backproject(g, w), tol, what=tag + " backproject")
 
 
 def test_iterate_is_deterministic_and_resumable(spectra):

@@ -9,14 +9,16 @@ import torch
 
 from workloads import make_inputs, PENALTY
 from workloads import geometry as Gw
+from tests.errors import rel_l2, rel_max
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
 def rel(a, b):
-    a, b = np.asarray(a, float), np.asarray(b, float)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    """The larger of the relative L2 error and the element-wise error (max-abs
+    relative to max |b|): a bound on it bounds both."""
+    return max(rel_l2(a, b), rel_max(a, b))
 
 
 def _plan(g, inp, prec):

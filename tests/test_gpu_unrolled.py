@@ -7,14 +7,16 @@ import pytest
 import torch
 
 from workloads import make_inputs, unrolled_inputs
+from tests.errors import rel_l2, rel_max
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
 def rel(a, b):
-    a, b = np.asarray(a, float), np.asarray(b, float)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    """The larger of the relative L2 error and the element-wise error (max-abs
+    relative to max |b|): a bound on it bounds both."""
+    return max(rel_l2(a, b), rel_max(a, b))
 
 
 def _plan(inp, prec):
@@ -124,3 +126,67 @@ def test_unrolled_batch_reduces_loss():
             L1 = loss_of(c0.detach() - step * grad)
         print(f"seed {seed}: loss {L0.item():.5e} -> {L1.item():.5e}")
         assert L1.item() < L0.item()
+
+
+@pytest.fixture(scope="module")
+def c5_oracle(orc):
+    """The oracle's unrolled reconstruction of the fan256 workload (seed 50):
+    ten iterations forward, then the chain of step VJPs back to c0 for the L2
+    loss on the non-metal voxels."""
+    inp = unrolled_inputs(50)
+    g = inp["geom"]
+    mask_o = orc.metal_trace(g, inp["metal"], inp["t"])[0]
+    n = 10
+    cs = [inp["c0"]]
+    for _ in range(n):
+        cs.append(orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], cs[-1], 1)[0])
+    keep = inp["keep"]
+    loss = float(np.sum(keep * (cs[-1] - inp["c_true"]) ** 2))
+    G = 2.0 * keep * (cs[-1] - inp["c_true"])
+    for k in range(n - 1, -1, -1):
+        G = orc.step_vjp(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], cs[k], G)
+    return inp, mask_o, cs[-1], loss, G
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-4), ("fp64", 1e-10)])
+def test_unrolled_fan256_ten_iterations_matches_oracle(c5_oracle, prec, tol):
+    """The unrolled-reconstruction workload at its own size (fan256, 256^2,
+    360 x 512 rays, ten iterations): reconstruction, loss and the gradient
+    with respect to c0 against the oracle chain, element by element."""
+    from paper_2202_00116_amd.autograd import unrolled_deam
+    inp, mask_o, c_o, loss_o, G_o = c5_oracle
+    plan = _plan(inp, prec)
+    c0 = torch.tensor(inp["c0"], device=DEV, requires_grad=True)
+    cn = unrolled_deam(c0, plan, torch.tensor(inp["d"], device=DEV), torch.tensor(mask_o, device=DEV),
+                       inp["Z"], 10)
+    keep = torch.tensor(inp["keep"], device=DEV)
+    loss = (keep * (cn - torch.tensor(inp["c_true"], device=DEV)) ** 2).sum()
+    loss.backward()
+    el = abs(loss.item() - loss_o) / loss_o
+    ec, eg = rel(cn.detach().cpu().numpy(), c_o), rel(c0.grad.cpu().numpy(), G_o)
+    print(f"fan256 {prec} 10 unrolled iterations: image {ec:.3e}, loss {el:.3e}, gradient {eg:.3e}")
+    assert ec <= tol and el <= tol and eg <= tol
+
+
+def test_unrolled_batch_of_eight_loss_matches_oracle(orc):
+    """The batch of the unrolled workload (seeds 50-57, fan256, ten
+    iterations, mixed precision): each case's loss against the oracle's."""
+    from paper_2202_00116_amd.autograd import unrolled_deam
+    worst = 0.0
+    for seed in range(50, 58):
+        inp = unrolled_inputs(seed)
+        g = inp["geom"]
+        mask_o = orc.metal_trace(g, inp["metal"], inp["t"])[0]
+        c_o, _ = orc.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"], inp["c0"], 10)
+        loss_o = float(np.sum(inp["keep"] * (c_o - inp["c_true"]) ** 2))
+        plan = _plan(inp, "mixed")
+        with torch.no_grad():
+            cn = unrolled_deam(torch.tensor(inp["c0"], device=DEV), plan,
+                               torch.tensor(inp["d"], device=DEV), torch.tensor(mask_o, device=DEV),
+                               inp["Z"], 10)
+            loss = float((torch.tensor(inp["keep"], device=DEV)
+                          * (cn - torch.tensor(inp["c_true"], device=DEV)) ** 2).sum())
+        e = abs(loss - loss_o) / loss_o
+        print(f"seed {seed}: loss {loss:.6e} oracle {loss_o:.6e} rel {e:.2e}")
+        worst = max(worst, e)
+    assert worst <= 1e-5

@@ -7,13 +7,16 @@ import torch
 
 from workloads import make_inputs
 from tests.test_oracle_dual import shifted_scan
+from tests.errors import rel_l2, rel_max
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+    """The larger of the relative L2 error and the element-wise error (max-abs
+    relative to max |b|): a bound on it bounds both."""
+    return max(rel_l2(a, b), rel_max(a, b))
 
 
 def _one_spectrum(I0, j):

@@ -46,6 +46,8 @@ def geometry_for(name: str) -> G.Geometry:
         return G.fan2d(64, 1.0, 64, 96)
     if name == "helical_small":  # small helical case: 64^2 x 16, 4 rows x 96 channels
         return G.helical3d(64, 1.0, 16, 1.0, 4, 96, 48, 2, 0.75, 2.0)
+    if name == "helical_mid":   # 96^2 x 24, 8 rows x 168 channels, 320 views/rot x 2, pitch 0.75
+        return G.helical3d(96, 1.0, 24, 1.0, 8, 168, 320, 2, 0.75, 1.5)
     raise KeyError(name)
 
 
@@ -57,6 +59,7 @@ WORKLOADS = {
     "fan256": (1e5, 40, 20),
     "fan64": (1e5, 11, 20),
     "helical_small": (1e5, 13, 10),
+    "helical_mid": (1e5, 14, 20),
 }
 
 
@@ -109,26 +112,37 @@ def phantom_for(name: str) -> MaterialPhantom:
                      E(sx * 95, 0, 24, 24, "trabecular_bone", "cortical_bone"),
                      E(sx * 95, 0, 10, 8, "steel", "trabecular_bone", theta=sx * 0.3)]
         return MaterialPhantom(objs)
-    if name in ("helical", "helical_small"):
-        s = 1.0 if name == "helical" else 0.12
-        zl, zh = -32.0 * (1.0 if name == "helical" else 0.25), 32.0 * (1.0 if name == "helical" else 0.25)
-        objs = [E(0, 0, 180 * s, 130 * s, "fat", "air", zlo=zl, zhi=zh),
-                E(0, 0, 170 * s, 120 * s, "water", "fat", zlo=zl, zhi=zh),
-                E(0, -20 * s, 24 * s, 24 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
-                E(0, -20 * s, 22 * s, 22 * s, "trabecular_bone", "cortical_bone", zlo=zl, zhi=zh),
-                E(0, -55 * s, 20 * s, 14 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
-                E(0, -55 * s, 9 * s, 7 * s, "water", "cortical_bone", zlo=zl, zhi=zh)]
-        ang = math.radians(15.0)
-        zpos = (-12.0, 12.0) if name == "helical" else (-3.0, 3.0)
-        for sx in (-1, 1):
-            d = (-sx * math.sin(ang), math.cos(ang), 0.0)
-            for z in zpos:
-                start = (sx * 18.0 * s, -75.0 * s, z)
-                half = 22.5 * s
-                c = (start[0] + half * d[0], start[1] + half * d[1], z)
-                objs.append(Cylinder(c, d, max(2.5 * s, 1.0), half, "titanium", "water"))
-        return MaterialPhantom(objs)
+    if name == "helical":
+        return spine_phantom(1.0, 32.0, 12.0)
+    if name == "helical_small":
+        return spine_phantom(0.12, 8.0, 3.0)
+    if name == "helical_mid":
+        return spine_phantom(0.18, 12.0, 4.5)
     raise KeyError(name)
+
+
+def spine_phantom(s, zhalf, zscrew):
+    """The helical workloads' phantom, in-plane lengths scaled by s: an
+    elliptic body (fat around water) over |z| <= zhalf, a vertebral body
+    (cortical shell, trabecular core), a posterior arch around the canal, and
+    four titanium screws converging at 15 degrees, at z = -zscrew and zscrew."""
+    zl, zh = -zhalf, zhalf
+    objs = [E(0, 0, 180 * s, 130 * s, "fat", "air", zlo=zl, zhi=zh),
+            E(0, 0, 170 * s, 120 * s, "water", "fat", zlo=zl, zhi=zh),
+            E(0, -20 * s, 24 * s, 24 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
+            E(0, -20 * s, 22 * s, 22 * s, "trabecular_bone", "cortical_bone", zlo=zl, zhi=zh),
+            E(0, -55 * s, 20 * s, 14 * s, "cortical_bone", "water", zlo=zl, zhi=zh),
+            E(0, -55 * s, 9 * s, 7 * s, "water", "cortical_bone", zlo=zl, zhi=zh)]
+    ang = math.radians(15.0)
+    zpos = (-zscrew, zscrew)
+    for sx in (-1, 1):
+        d = (-sx * math.sin(ang), math.cos(ang), 0.0)
+        for z in zpos:
+            start = (sx * 18.0 * s, -75.0 * s, z)
+            half = 22.5 * s
+            c = (start[0] + half * d[0], start[1] + half * d[1], z)
+            objs.append(Cylinder(c, d, max(2.5 * s, 1.0), half, "titanium", "water"))
+    return MaterialPhantom(objs)
 
 
 def _views_chunks(n_views, per):
