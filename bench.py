@@ -5,10 +5,13 @@ metal-trace substitution, 4-channel backprojection, FP64 update and the FP64
 I-divergence reduction) over the whole synthetic scan, with every input
 resident in HBM.  Prints one JSON line.
 
-Default workload: the 2D fan-beam case (512 x 512 at 0.98 mm, 984 views x 816
-channels, 90/140 kVp spectra on 1-keV bins from 20 to 140 keV, pelvis-like
-phantom with two steel implants, I0 = 2e5).  `--workload helical` runs the
-3D helical case (512 x 512 x 64, 16 x 816 detector, 4608 views).
+Default workload: the 3D helical cone-beam case (512 x 512 x 64 at
+0.98 x 0.98 x 1 mm, 16 rows x 816 channels, 1152 views per turn over four
+turns at pitch 0.5, 90/140 kVp spectra on 1-keV bins from 20 to 140 keV,
+spine-like phantom with four titanium screws, I0 = 2e5).  The 2D fan-beam
+case (512 x 512, 984 views x 816 channels) and the unrolled reconstruction
+are measured as secondary blocks.  `--workload fan512` makes the fan-beam
+case the headline.
 """
 from __future__ import annotations
 
@@ -317,6 +320,13 @@ def measure(workload, K, W, K64, dev, log, extras=True):
                 "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
                 "traffic": traffic, "kernel": dom, "ops_per_launch": ops[dom],
                 "segments": S, "avg_launch_ms": times[dom],
+                "frac_kind": "algorithmic lane-ops of one launch (forward + energy sums: 8 per "
+                             "Siddon segment + 11 per ray and energy bin + 40 per ray; "
+                             "backprojection: 10 per segment) / its HIP-event time / the VALU "
+                             "lane peak (256 CU x 64 lanes x 2.4 GHz); not issued instructions",
+                "traffic_source": None if traffic is None else
+                f"profiles/{dom}_{workload}_pmc.txt: rocprofv3 FETCH_SIZE + WRITE_SIZE per "
+                f"dispatch scaled by a 1 GiB copy's counts, read from the committed summary",
                 "traffic_GBps": None if traffic is None else traffic / (times[dom] * 1e-3) / 1e9}
     it_ops, it_bytes = iteration_model(g, S, nE)
     t_valu, t_hbm = it_ops / PEAK_LANE_OPS, it_bytes / PEAK_HBM
@@ -382,19 +392,123 @@ def measure_unrolled(dev, log, batch=8, n_iter=10, reps=3):
             "iterations_per_s": batch * n_iter / t}
 
 
+def view_block(g, n):
+    """The middle n views of a scan as a scan of their own: the same rays
+    (the helix is centred on the scan's middle view, so a centred block keeps
+    every source position); returns (geometry, first view)."""
+    import dataclasses
+    v0 = (g.n_views - n) // 2
+    if (g.n_views - n) % 2:
+        n += 1
+    beta0 = g.beta0 + 2.0 * math.pi * v0 / g.views_per_rot
+    return dataclasses.replace(g, n_views=n, beta0=beta0), v0
+
+
+def oracle_sample(g, inp, mask_np, n_views, plan_cls, dev, one_core_views=None):
+    """The FP64 oracle on a bounded sample of the workload: one DEAM iteration
+    over the middle n_views views (forward, poly-mean and backprojection of
+    those rays, update of the whole image) on all host cores, scaled to the
+    whole scan by its ray count (the update is timed on its own and counted
+    once).  The GPU (mixed precision) runs the same iteration on the same
+    inputs, and the two images and objectives are compared over the whole
+    volume.  Optionally a smaller sample on one core."""
+    import torch
+    from oracle import oracle as O
+    gs, v0 = view_block(g, n_views)
+    per_view = g.n_rows * g.n_cols
+    sl = slice(v0 * per_view, (v0 + gs.n_views) * per_view)
+    d_s = np.ascontiguousarray(inp["d"][:, sl])
+    m_s = np.ascontiguousarray(mask_np[sl])
+    Z = inp["Z"]
+    t0 = time.perf_counter()
+    c_o, h_o, b_o = O.iterate(gs, inp["I0"], inp["mu"], d_s, m_s, Z, inp["c0"], 1, want_b=True)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.update(b_o, Z, inp["c0"])
+    t_u = time.perf_counter() - t0
+    scale = g.n_views / gs.n_views
+    t_full = scale * max(t_s - t_u, 0.0) + t_u
+    # the GPU on the same sample
+    plan = plan_cls(gs, inp["I0"], inp["mu"], "mixed")
+    c = torch.from_numpy(inp["c0"]).to(dev)
+    hist = torch.zeros(1, dtype=torch.float64, device=dev)
+    plan.iterate(c, torch.from_numpy(d_s).to(dev), torch.from_numpy(m_s).to(dev), Z, 1, hist)
+    c = c.cpu().numpy()
+    del plan
+    bh = b_o[2:]
+    res = np.all(bh >= 1e-6 * bh.max(axis=1, keepdims=True), axis=0)
+    e = np.abs(c - c_o)
+    cmax = np.abs(c_o).max()
+    err = {"sample": f"one DEAM iteration over views {v0}-{v0 + gs.n_views - 1} of the scan "
+                     f"({gs.n_rays} rays, the whole image), mixed precision against the FP64 oracle",
+           "image_rel_l2": float(np.linalg.norm(c - c_o) / np.linalg.norm(c_o)),
+           "image_max_abs_rel": float(e[:, res].max() / cmax),
+           "image_max_abs_rel_all_voxels": float(e.max() / cmax),
+           "resolved_voxels": int(res.sum()), "voxels": int(res.size),
+           "objective_rel": float(abs(hist.item() - h_o[0]) / abs(h_o[0]))}
+    base = {"value": 1.0 / t_full, "unit": "iterations/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 FP64 oracle DEAM iteration over the middle {gs.n_views} of {g.n_views} views "
+                      f"({t_s:.1f} s, of which {t_u:.2f} s the whole-image update), scaled by the "
+                      f"ray count to the whole scan: {t_full:.1f} s per iteration"}
+    if one_core_views:
+        g1, w0 = view_block(g, one_core_views)
+        sl1 = slice(w0 * per_view, (w0 + g1.n_views) * per_view)
+        n_all = O.num_threads()
+        O.set_num_threads(1)
+        t0 = time.perf_counter()
+        _, _, b1 = O.iterate(g1, inp["I0"], inp["mu"], np.ascontiguousarray(inp["d"][:, sl1]),
+                             np.ascontiguousarray(mask_np[sl1]), Z, inp["c0"], 1, want_b=True)
+        t1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.update(b1, Z, inp["c0"])
+        tu1 = time.perf_counter() - t0
+        O.set_num_threads(n_all)
+        t1_full = g.n_views / g1.n_views * max(t1 - tu1, 0.0) + tu1
+        base["one_core"] = {"value": 1.0 / t1_full, "unit": "iterations/s", "cores": 1,
+                            "sample": f"1 FP64 oracle iteration over the middle {g1.n_views} views "
+                                      f"({t1:.1f} s), scaled: {t1_full:.0f} s per iteration"}
+    return base, err
+
+
+def oracle_full_iterations(g, inp, mask_np, n_it, plan, d, mask, c0, dev):
+    """The FP64 oracle over n_it whole iterations on all host cores (a workload
+    small enough for that), and the GPU's n_it iterations against it."""
+    import torch
+    from oracle import oracle as O
+    Z = inp["Z"]
+    t0 = time.perf_counter()
+    c_o, h_o = O.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_np, Z, inp["c0"], n_it)
+    t_cpu = time.perf_counter() - t0
+    cg = c0.clone()
+    hg = torch.zeros(n_it, dtype=torch.float64, device=dev)
+    plan.iterate(cg, d, mask, Z, n_it, hg)
+    cg = cg.cpu().numpy()
+    base = {"value": n_it / t_cpu, "unit": "iterations/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{n_it} whole FP64 oracle DEAM iterations from the cold start ({t_cpu:.1f} s)"}
+    err = {"iterations": n_it,
+           "image_rel_l2": float(np.linalg.norm(cg - c_o) / np.linalg.norm(c_o)),
+           "image_max_abs_rel": float(np.abs(cg - c_o).max() / np.abs(c_o).max()),
+           "objective_rel": float(np.abs(hg.cpu().numpy() - h_o).max() / abs(h_o[0]))}
+    return base, err
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fan512", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--workload", default="helical", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=4,
+                    help="whole oracle iterations of the fan-beam workload")
+    ap.add_argument("--cpu-sample-views", type=int, default=144,
+                    help="views of the helical oracle sample (all host cores)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="measure the main iteration only (skip the penalised, MAR and variant "
-                         "measurements and the helical and unrolled-reconstruction workloads)")
-    ap.add_argument("--helical-steps", type=int, default=10)
+                         "measurements and the secondary and unrolled-reconstruction workloads)")
+    ap.add_argument("--secondary-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -417,7 +531,7 @@ def main():
                           "launches": launches, "copy_GBps": bw / 1e9}))
         return
     K, W = args.steps, args.warmup
-    K64 = args.fp64_steps if args.fp64_steps is not None else max(2, K // 4)
+    K64 = args.fp64_steps if args.fp64_steps is not None else max(3, K // 4)
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
     copy_bw, _ = copy_bandwidth(dev)
     log(f"device copy: {copy_bw / 1e9:.0f} GB/s (read + write)")
@@ -458,47 +572,43 @@ def main():
         "cpu_baseline": None,
     }
 
-    # --- CPU baseline (the FP64 oracle) ---------------------------------------------
+    # --- CPU baseline (the FP64 oracle) and the error against it --------------------
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        n_it = args.cpu_iters
         mask_np = mask.cpu().numpy()
-        t0 = time.perf_counter()
-        c_o, h_o = O.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_np, Z, inp["c0"], n_it)
-        t_cpu = time.perf_counter() - t0
-        cg = c0.clone()
-        hg = torch.zeros(n_it, dtype=torch.float64, device=dev)
-        plan.iterate(cg, d, mask, Z, n_it, hg)
-        cg = cg.cpu().numpy()
-        err = float(np.linalg.norm(cg - c_o) / np.linalg.norm(c_o))
-        herr = float(np.abs(hg.cpu().numpy() - h_o).max() / abs(h_o[0]))
-        out["cpu_baseline"] = {"value": n_it / t_cpu, "unit": "iterations/s",
-                               "cores": O.num_threads(), "kind": "oracle",
-                               "sample": f"{n_it} full FP64 oracle DEAM iterations of the {args.workload} "
-                                         f"workload from the cold start ({t_cpu:.1f} s)"}
-        out["error_vs_oracle"] = {"iterations": n_it, "image_rel_l2": err, "objective_rel": herr}
-        # the same oracle on one core, one iteration
-        n_all = O.num_threads()
-        O.set_num_threads(1)
-        t0 = time.perf_counter()
-        O.iterate(g, inp["I0"], inp["mu"], inp["d"], mask_np, Z, inp["c0"], 1)
-        t_one = time.perf_counter() - t0
-        O.set_num_threads(n_all)
-        out["cpu_baseline"]["one_core"] = {"value": 1.0 / t_one, "unit": "iterations/s", "cores": 1,
-                                           "sample": f"1 FP64 oracle iteration ({t_one:.1f} s)"}
+        if g.kind == 1:
+            out["cpu_baseline"], out["error_vs_oracle"] = oracle_sample(
+                g, inp, mask_np, args.cpu_sample_views, type(plan), dev,
+                one_core_views=max(1, args.cpu_sample_views // 8))
+        else:
+            out["cpu_baseline"], out["error_vs_oracle"] = oracle_full_iterations(
+                g, inp, mask_np, args.cpu_iters, plan, d, mask, c0, dev)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} it/s on "
+            f"{out['cpu_baseline']['cores']} cores")
 
-    # --- secondary workloads: the 3D helical case and the unrolled reconstruction
-    if not args.no_secondary and args.workload != "helical":
+    # --- secondary workloads: the other geometry and the unrolled reconstruction
+    if not args.no_secondary:
+        other = "fan512" if args.workload == "helical" else "helical"
         del m, plan, d, mask, c0
         torch.cuda.empty_cache()
-        h = measure("helical", args.helical_steps, 1, 1, dev, log)
-        out["helical"] = {"workload": f"helical: {WORKLOAD_DESC['helical']}",
-                          "iterations_per_s": 1.0 / h["t_step"], "ms_per_step": h["t_step"] * 1e3,
-                          "steps": args.helical_steps, "grays_per_s": h["grays"],
-                          "grays_per_s_1ch": h["grays_1ch"],
-                          "kernel_ms": h["kernel_ms"], "fp64": h["fp64"],
-                          "speedup_mixed_vs_fp64": h["speedup"], "roofline": h["roofline"],
-                          "iteration_roofline": h["iteration"], "penalized": h["penalized"]}
+        K2 = args.secondary_steps
+        h = measure(other, K2, 1, max(3, K2 // 4), dev, log)
+        blk = {"workload": f"{other}: {WORKLOAD_DESC[other]}",
+               "iterations_per_s": 1.0 / h["t_step"], "ms_per_step": h["t_step"] * 1e3,
+               "steps": K2, "grays_per_s": h["grays"], "grays_per_s_1ch": h["grays_1ch"],
+               "kernel_ms": h["kernel_ms"], "fp64": h["fp64"],
+               "speedup_mixed_vs_fp64": h["speedup"], "roofline": h["roofline"],
+               "iteration_roofline": h["iteration"], "penalized": h["penalized"],
+               "mar_init": h["mar_init"], "variants": h["variants"]}
+        if not args.no_cpu_baseline:
+            hg, hinp = h["inp"]["geom"], h["inp"]
+            hmask = h["mask"].cpu().numpy()
+            if hg.kind == 1:
+                blk["cpu_baseline"], blk["error_vs_oracle"] = oracle_sample(
+                    hg, hinp, hmask, args.cpu_sample_views, type(h["plan"]), dev)
+            else:
+                blk["cpu_baseline"], blk["error_vs_oracle"] = oracle_full_iterations(
+                    hg, hinp, hmask, args.cpu_iters, h["plan"], h["d"], h["mask"], h["c0"], dev)
+        out[other] = blk
         del h
         torch.cuda.empty_cache()
     if not args.no_secondary:

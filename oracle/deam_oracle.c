@@ -502,6 +502,14 @@ void orc_metal_trace(const orc_geom* g, const unsigned char* M, double t,
 int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
                 const double* d, const unsigned char* mask, const double Z[2],
                 int n_iter, double* c, double* obj_hist) {
+  return orc_iterate_b(g, nE, I0, mu, d, mask, Z, n_iter, c, obj_hist, NULL);
+}
+
+/* orc_iterate that also returns the backprojections b~_1, b~_2, b^_1, b^_2
+ * ([4][V]) of the last iteration in b_last (may be NULL). */
+int orc_iterate_b(const orc_geom* g, int nE, const double* I0, const double* mu,
+                  const double* d, const unsigned char* mask, const double Z[2],
+                  int n_iter, double* c, double* obj_hist, double* b_last) {
   long R = orc_n_rays(g), V = orc_n_voxels(g);
   double* l = (double*)malloc(sizeof(double) * (size_t)(2 * R));
   double* w = (double*)malloc(sizeof(double) * (size_t)(4 * R));
@@ -514,6 +522,7 @@ int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
     if (obj_hist) obj_hist[k] = orc_sum(R, obj);
     orc_backproject(g, 4, w, b);
     orc_update(V, b, Z, c);
+    if (b_last && k == n_iter - 1) memcpy(b_last, b, sizeof(double) * (size_t)(4 * V));
   }
   free(l); free(w); free(obj); free(b);
   return 0;

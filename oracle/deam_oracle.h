@@ -55,6 +55,9 @@ void orc_metal_trace(const orc_geom* g, const unsigned char* M, double t,
 int orc_iterate(const orc_geom* g, int nE, const double* I0, const double* mu,
                 const double* d, const unsigned char* mask, const double Z[2],
                 int n_iter, double* c, double* obj_hist);
+int orc_iterate_b(const orc_geom* g, int nE, const double* I0, const double* mu,
+                  const double* d, const unsigned char* mask, const double Z[2],
+                  int n_iter, double* c, double* obj_hist, double* b_last);
 double orc_objective(const orc_geom* g, int nE, const double* I0, const double* mu,
                      const double* d, const unsigned char* mask, const double* c, int mode);
 double orc_fair(double t, double delta);

@@ -120,6 +120,9 @@ def _setup(L):
     L.orc_metal_trace.argtypes = [G, u1, C.c_double, u1, C.c_void_p]
     L.orc_iterate.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p]
     L.orc_iterate.restype = C.c_int
+    L.orc_iterate_b.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int, d1, C.c_void_p,
+                                C.c_void_p]
+    L.orc_iterate_b.restype = C.c_int
     L.orc_objective.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_int]
     L.orc_objective.restype = C.c_double
     L.orc_nll_grad.argtypes = [G, C.c_int, d1, d1, d1, C.c_void_p, d1, C.c_void_p]
@@ -257,17 +260,20 @@ def metal_trace(g, M, t):
     return mask, T
 
 
-def iterate(g, I0, mu, d, mask, Z, c0, n_iter):
-    """Run n_iter DEAM iterations from c0; returns (c, objective history)."""
+def iterate(g, I0, mu, d, mask, Z, c0, n_iter, want_b=False):
+    """Run n_iter DEAM iterations from c0; returns (c, objective history), and
+    with want_b also the last iteration's backprojections b (4, V)
+    (b~_1, b~_2, b^_1, b^_2)."""
     c = _f64(c0).copy()
     hist = np.zeros(max(n_iter, 1))
+    b = np.zeros((4, g.n_voxels)) if want_b else None
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
-    rc = lib().orc_iterate(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
-                           _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
-                           n_iter, c.reshape(-1), hist.ctypes.data_as(C.c_void_p))
+    rc = lib().orc_iterate_b(C.byref(geom_struct(g)), I0.shape[-1], _f64(I0).reshape(-1),
+                             _f64(mu).reshape(-1), _f64(d).reshape(-1), _ptr(m), _f64(Z),
+                             n_iter, c.reshape(-1), hist.ctypes.data_as(C.c_void_p), _ptr(b))
     if rc != 0:
         raise MemoryError("oracle iterate allocation failed")
-    return c, hist[:n_iter]
+    return (c, hist[:n_iter], b) if want_b else (c, hist[:n_iter])
 
 
 def step_vjp(g, I0, mu, d, mask, Z, c, G):

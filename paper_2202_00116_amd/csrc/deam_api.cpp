@@ -356,14 +356,17 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
       const double sbb = yd ? su : sv, db = yd ? du : dv;
       const double mb = db / da;
       deam::RayXY<double> t;
-      t.b0 = sbb - sa * mb;
+      const double b0 = sbb - sa * mb;            // lateral coordinate at a = 0
+      const double na = yd ? g.ny : g.nx;         // extent of the driving axis
+      const double ib = std::floor(std::fmin(std::fmax(b0 + 0.5 * na * mb, -1e6), 1e6));
+      t.b0 = b0 - ib;
       t.mb = mb;
       t.imb = mb != 0.0 ? 1.0 / mb : 1e30;
       t.sa = sa;
       t.ida = 1.0 / da;
       t.iadb = db != 0.0 ? 1.0 / std::fabs(db) : 1e30;
       t.yd = yd ? 1.0 : 0.0;
-      t.pad = 0.0;
+      t.ib = ib;
       const size_t i = (size_t)v * g.n_cols + k;
       rays64[i] = t;
       if (!rays32.empty()) {
@@ -375,7 +378,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
         f.ida = (float)t.ida;
         f.iadb = (float)t.iadb;
         f.yd = (float)t.yd;
-        f.pad = 0.f;
+        f.ib = (float)t.ib;
       }
     }
   }

@@ -13,15 +13,20 @@ namespace deam {
 // In-plane description of the ray of one (view, channel), in grid units
 // (voxel index coordinates).  The ray is walked along its driving axis a
 // (y if |dy| >= |dx| in grid units, else x) and its lateral coordinate is
-// b(a) = b0 + a*mb.  Computed once per plan in FP64, stored in the plan
-// precision; shared by all detector rows of a helical channel.
+// b(a) = ib + b0 + a*mb.  The integer origin ib is the lateral pixel at the
+// middle of the grid's driving range, so that b0 + a*mb stays small along
+// the ray: its rounding (and with it the error of every lateral crossing,
+// that rounding divided by |mb|) is then set by the lateral distance
+// travelled, not by the grid size, which matters for rays nearly parallel
+// to a grid axis in FP32.  Computed once per plan in FP64, stored in the
+// plan precision; shared by all detector rows of a helical channel.
 template <typename T>
 struct RayXY {
-  T b0, mb, imb;  // lateral line and 1/mb (huge when mb == 0)
+  T b0, mb, imb;  // lateral line relative to ib, and 1/mb (huge when mb == 0)
   T sa, ida;      // driving coordinate of the source, 1/da (da = in-plane run in grid units)
   T iadb;         // 1/|db| (huge when db == 0)
   T yd;           // 1 when a = y (rows), 0 when a = x
-  T pad;
+  T ib;           // integer lateral origin (exact in the plan precision)
 };
 
 // Geometry as the kernels see it.

@@ -116,31 +116,48 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Ray {
-  T b0, mb;       // lateral grid coordinate b(a) = b0 + a*mb
+  T b0, mb;       // lateral grid coordinate b(a) = ib + b0 + a*mb: the walk
+                  // counts lateral pixels from the ray's origin ib
   T imb;          // 1/mb (huge when mb = 0)
-  T w0, mw, imw;  // axial grid coordinate w(a) = w0 + a*mw, imw = 1/|mw|
+  T w0, mw, imw;  // axial grid coordinate w(a) = iw + w0 + a*mw, imw = 1/|mw|: the
+                  // walk counts slices from the ray's origin iw
   T La, Lb;       // mm of ray per unit of a, per unit of b
   T alo, ahi;     // range of a inside the clip box
   int ydrive;     // 1: a = y (rows) and b = x; 0: a = x and b = y
+  int ib;         // lateral origin: lateral pixel indices of the walk are relative to it
+  int iw;         // axial origin (3D): slice indices of the walk are relative to it
 };
 
 // Ray (v, r, k) clipped to the voxel box [lo, hi) (grid units, axes x, y, z).
-// Returns false if the ray misses the box.
+// Returns false if the ray misses the box.  Lateral pixel indices of the
+// walk (and the lateral bounds given to walk_row) are relative to ry.ib, and
+// in 3D slice indices (and the axial bounds) relative to ry.iw, the slice at
+// the middle of the ray's driving range; the axial line is set up in FP64
+// from the FP64 ray table, so that its rounding, and with it the error of a
+// slice crossing (that rounding divided by |mw|, which is small for rays
+// close to the slice planes), is set by the axial distance travelled.
 template <typename T>
 __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
                                          int v, int r, int k, int lox, int loy, int loz, int hix,
                                          int hiy, int hiz, Ray<T>& ry) {
   const RayXY<T> t = rays[(int64_t)v * G.n_cols + k];
   const bool yd = t.yd != (T)0;
+  const int ib = (int)t.ib;
   const T Lr = (T)G.row[4 * r + 1];
   T mw = 0, w0 = (T)0.5, rmw = 0;
+  int iw = 0;
   if (G.is3d) {
-    mw = (T)G.row[4 * r] * t.ida;
-    w0 = (T)G.view[4 * v + 3] - t.sa * mw;
+    const RayXY<double>& t64 = G.rays64[(int64_t)v * G.n_cols + k];
+    const double mw64 = G.row[4 * r] * t64.ida;
+    const double w064 = G.view[4 * v + 3] - t64.sa * mw64;        // w at a = 0
+    const double amid = 0.5 * (yd ? G.ny : G.nx);
+    iw = (int)floor(fmin(fmax(fma(amid, mw64, w064), -1e6), 1e6));
+    mw = (T)mw64;
+    w0 = (T)(w064 - (double)iw);
     rmw = mw != (T)0 ? (T)1 / mw : (T)0;
   }
   const T alo_box = (T)(yd ? loy : lox), ahi_box = (T)(yd ? hiy : hix);
-  const T blo = (T)(yd ? lox : loy), bhi = (T)(yd ? hix : hiy);
+  const T blo = (T)((yd ? lox : loy) - ib), bhi = (T)((yd ? hix : hiy) - ib);
   T alo = alo_box, ahi = ahi_box;
   if (t.mb != (T)0) {
     const T t0 = (blo - t.b0) * t.imb, t1 = (bhi - t.b0) * t.imb;
@@ -150,11 +167,12 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
     return false;
   }
   if (G.is3d) {
+    const T wlo = (T)(loz - iw), whi = (T)(hiz - iw);
     if (mw != (T)0) {
-      const T t0 = ((T)loz - w0) * rmw, t1 = ((T)hiz - w0) * rmw;
+      const T t0 = (wlo - w0) * rmw, t1 = (whi - w0) * rmw;
       alo = fmax(alo, fmin(t0, t1));
       ahi = fmin(ahi, fmax(t0, t1));
-    } else if (!(w0 >= (T)loz && w0 < (T)hiz)) {
+    } else if (!(w0 >= wlo && w0 < whi)) {
       return false;
     }
   }
@@ -170,6 +188,8 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   ry.alo = alo;
   ry.ahi = ahi;
   ry.ydrive = yd ? 1 : 0;
+  ry.ib = ib;
+  ry.iw = iw;
   return true;
 }
 
@@ -261,6 +281,9 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   const bool hit = valid && make_ray<T>(G, rays, v, r, k, 0, 0, 0, G.nx, G.ny, nzz, ry);
   const uint32_t base = ry.ydrive ? 0u : xoff;
   const int nb = ry.ydrive ? G.nx : G.ny;
+  // lateral pixel range [blo, bhi] relative to the ray's origin ry.ib (0 for
+  // a lane without a ray); addresses add the origin back
+  const int blo = -ry.ib, bhi = nb - 1 - ry.ib;
   const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
   const uint32_t rstep = (uint32_t)nb * E;
   const char* __restrict__ cpb = (const char*)cp;
@@ -276,9 +299,11 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   const int q1 = hit ? -ifloor(-ry.ahi) : -(1 << 30);
   T tp = ry.alo;                                         // start of the current step
   T bp = fma(tp, ry.mb, ry.b0);                          // lateral coordinate there
-  int A = clampi(ifloor(bp), 0, nb - 1);
+  int A = clampi(ifloor(bp), blo, bhi);
+  // slices relative to the ray's axial origin ry.iw (0 in 2D)
+  const int wlo = -ry.iw, whi = nzz - 1 - ry.iw;
   int C = 0;
-  if constexpr (Z3) C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), 0, nzz - 1);
+  if constexpr (Z3) C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), wlo, whi);
   uint64_t rest = 0;   // 3D: deferred steps, bit = step - qw
   int qw = 0;
   T fa = 0;
@@ -288,14 +313,14 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
     fa += (T)1;
     const T tn = clampf(fa, ry.alo, ry.ahi);
     const T bn = fma(tn, ry.mb, ry.b0);
-    const int B = clampi(ifloor(bn), 0, nb - 1);
+    const int B = clampi(ifloor(bn), blo, bhi);
     T ds = tn - tp;
     const uint32_t rq = row;
     row += rstep;
     if constexpr (Z3) {
       // (clamped: a step that reaches a face of the volume stays in the edge
       // slice up to the ray's end)
-      const int D = clampi(ifloor(fma(tn, ry.mw, ry.w0)), 0, nzz - 1);
+      const int D = clampi(ifloor(fma(tn, ry.mw, ry.w0)), wlo, whi);
       if (D != C) {
         rest |= 1ull << (q - qw);
         ds = (T)0;
@@ -314,7 +339,8 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   };
   const T iLa = (T)1 / ry.La;
   auto visit = [&](int ia, int ib, int iw, T h) {
-    const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
+    const T2 cv = cp[base + (uint32_t)(iw + ry.iw) * plane + (uint32_t)ia * (uint32_t)nb +
+                     (uint32_t)(ib + ry.ib)];
     p1 = fma(h * iLa, cv.x, p1);
     p2 = fma(h * iLa, cv.y, p2);
   };
@@ -322,7 +348,7 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
     while (rest != 0ull) {
       const int bit = __ffsll((unsigned long long)rest) - 1;
       rest &= rest - 1ull;
-      walk_row<T, true, false>(ry, qw + bit, 0, nb, 0, nzz, visit);
+      walk_row<T, true, false>(ry, qw + bit, blo, bhi + 1, wlo, whi + 1, visit);
     }
   };
   // the lanes of a wave walk the same plane rows together (a common range),
@@ -333,7 +359,9 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
   if (qlo >= qhi) return;
   qw = qlo;
   fa = (T)qlo;
-  row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)C * plane) * E;
+  // (the unsigned offsets wrap for a negative relative pixel; sums with the
+  // origin's offset are the true, in-range offsets)
+  row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)(C + ry.iw) * plane + (uint32_t)ry.ib) * E;
   int q = qlo;
   int groups = 0;
   // gathers and sums of four steps: all gathers before the sums.  2D float
@@ -437,14 +465,14 @@ __device__ void project_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
       T e = 0;
       auto sync = [&]() {
         bp = fma((T)q, ry.mb, ry.b0);
-        A = clampi(ifloor(bp), 0, nb - 1);
+        A = clampi(ifloor(bp), blo, bhi);
         e = sg > 0 ? ((T)(A + 1) - bp) * iab : (sg < 0 ? (bp - (T)A) * iab : (T)1e30);
       };
       auto istep = [&](uint32_t& oA, uint32_t& oB, T& dA, T& dB) {
         const bool cr = e < (T)1;
         dA = clampf(e, (T)0, (T)1);
         dB = (T)1 - dA;
-        const int B = clampi(A + (cr ? sg : 0), 0, nb - 1);
+        const int B = clampi(A + (cr ? sg : 0), blo, bhi);
         oA = row + (uint32_t)A * E;
         oB = row + (uint32_t)B * E;
         row += rstep;
@@ -796,6 +824,10 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
   if (valid) t = rays[(int64_t)v * G.n_cols + k];
   const bool yd = t.yd != (T)0;
   const int nb = yd ? G.nx : G.ny, na = yd ? G.ny : G.nx;
+  // lateral pixels are counted from the ray's origin t.ib (see RayXY):
+  // [blo, bhi] is the grid's lateral range in that frame
+  const int ib = (int)t.ib;
+  const int blo = -ib, bhi = nb - 1 - ib;
   const uint32_t base = yd ? 0u : xoff;
   const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
   const uint32_t pstep = plane * E, rstep = (uint32_t)nb * E;
@@ -814,10 +846,10 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
   T alo = 0, ahi = (T)na;
   bool hit = valid;
   if (t.mb != (T)0) {
-    const T t0 = ((T)0 - t.b0) * t.imb, t1 = ((T)nb - t.b0) * t.imb;
+    const T t0 = ((T)blo - t.b0) * t.imb, t1 = ((T)(bhi + 1) - t.b0) * t.imb;
     alo = fmax(alo, fmin(t0, t1));
     ahi = fmin(ahi, fmax(t0, t1));
-  } else if (!(t.b0 >= (T)0 && t.b0 < (T)nb)) {
+  } else if (!(t.b0 >= (T)blo && t.b0 < (T)(bhi + 1))) {
     hit = false;
   }
   hit = hit && ahi > alo;
@@ -835,7 +867,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
   uint32_t zo[RG], rest[RG];
   T tp = alo;
   T bp = fma(tp, t.mb, t.b0);
-  int A = clampi(ifloor(bp), 0, nb - 1);
+  int A = clampi(ifloor(bp), blo, bhi);
   {
     const T u = (tp - t.sa) * t.ida;
 #pragma unroll
@@ -855,7 +887,9 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
 
   if (qlo < qhi) {
     T fa = (T)qlo;
-    uint32_t row = (base + (uint32_t)qlo * (uint32_t)nb) * E;
+    // byte offset of lateral pixel 0 of the ray's frame (the unsigned sums
+    // with a negative relative pixel wrap to the true offsets)
+    uint32_t row = (base + (uint32_t)qlo * (uint32_t)nb + (uint32_t)ib) * E;
     int qw = qlo;
     // the fast walk's lengths and offsets of plane step q (identical
     // arithmetic to the walk itself)
@@ -863,11 +897,11 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
       const T ta = clampf((T)q, alo, ahi);
       tn = clampf((T)(q + 1), alo, ahi);
       const T ba = fma(ta, t.mb, t.b0), bn = fma(tn, t.mb, t.b0);
-      const int Aq = clampi(ifloor(ba), 0, nb - 1), Bq = clampi(ifloor(bn), 0, nb - 1);
+      const int Aq = clampi(ifloor(ba), blo, bhi), Bq = clampi(ifloor(bn), blo, bhi);
       const T ds = tn - ta;
       dA = (Bq == Aq) ? ds : clamp0(((T)max(Aq, Bq) - ba) * t.imb, ds);
       dB = ds - dA;
-      const uint32_t rq = (base + (uint32_t)q * (uint32_t)nb) * E;
+      const uint32_t rq = (base + (uint32_t)q * (uint32_t)nb + (uint32_t)ib) * E;
       oA = rq + (uint32_t)Aq * E;
       oB = rq + (uint32_t)Bq * E;
     };
@@ -889,6 +923,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
         ry.alo = alo;
         ry.ahi = ahi;
         ry.ydrive = yd ? 1 : 0;
+        ry.ib = ib;
         if (ry.mw != (T)0) {
           const T z0 = ((T)0 - ry.w0) * rmw, z1 = ((T)nzz - ry.w0) * rmw;
           ry.alo = fmax(ry.alo, fmin(z0, z1));
@@ -897,8 +932,9 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           ry.ahi = ry.alo;
         }
         T e1 = 0, e2 = 0;
-        auto visit = [&](int ia, int ib, int iw, T h) {
-          const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb + (uint32_t)ib];
+        auto visit = [&](int ia, int jb, int iw, T h) {
+          const T2 cv = cp[base + (uint32_t)iw * plane + (uint32_t)ia * (uint32_t)nb +
+                           (uint32_t)(jb + ib)];
           e1 = fma(h * iLa[j], cv.x, e1);
           e2 = fma(h * iLa[j], cv.y, e2);
         };
@@ -914,7 +950,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
           const T2 vB = *(const T2*)(cpb + (uint32_t)(oB + z));
           e1 -= fma(dA, vA.x, dB * vB.x);
           e2 -= fma(dA, vA.y, dB * vB.y);
-          walk_row<T, true, false>(ry, q, 0, nb, 0, nzz, visit);
+          walk_row<T, true, false>(ry, q, blo, bhi + 1, 0, nzz, visit);
         }
         p1[j] += e1;
         p2[j] += e2;
@@ -925,7 +961,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
       fa += (T)1;
       const T tn = clampf(fa, alo, ahi);
       const T bn = fma(tn, t.mb, t.b0);
-      const int B = clampi(ifloor(bn), 0, nb - 1);
+      const int B = clampi(ifloor(bn), blo, bhi);
       const T ds = tn - tp;
       const T dA = (B == A) ? ds : clamp0(((T)max(A, B) - bp) * t.imb, ds);
       const T dB = ds - dA;
@@ -1339,7 +1375,8 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       for (int c = 0; c < NCH; ++c) wa[c] = w[c * G.R + ray] * scl[c] * ry.La;
       const bool yd = ry.ydrive != 0;
       const int la = yd ? ty0 : tx0;
-      const int lbb = yd ? tx0 : ty0, hb = yd ? tx1 : ty1;
+      // the tile's lateral range in the ray's frame (pixels relative to ry.ib)
+      const int lbb = (yd ? tx0 : ty0) - ry.ib, hb = (yd ? tx1 : ty1) - ry.ib;
       const int sa = yd ? RS : 1, sbs = yd ? 1 : RS;
       // lb: byte offset of the voxel in channel 0; da: length in units of
       // the driving axis; quantised terms are 32-bit halves when packed,
@@ -1391,10 +1428,12 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       const int sb8 = 8 * sbs;
       // byte offset of lateral index 0 in the current plane row and slice
       int row8 = 8 * (q0 * sa - lbb * sbs);
+      // the tile's slices in the ray's axial frame (relative to ry.iw)
+      const int tzl = tz0 - ry.iw, tzh = tz1 - ry.iw;
       int C = 0, cs = 0;
       if constexpr (Z3) {
-        C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), tz0, tz1 - 1);
-        row8 += 8 * (C - tz0) * TXY;
+        C = clampi(ifloor(fma(tp, ry.mw, ry.w0)), tzl, tzh - 1);
+        row8 += 8 * (C - tzl) * TXY;
         cs = ry.mw > (T)0 ? 1 : -1;
       }
       // 3D: the step that holds the next crossing of a slice plane inside the
@@ -1405,7 +1444,7 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       // `lo`, the step being walked (a crossing is never skipped).
       auto next_cross = [&](int lo) -> int {
         const int wb = cs > 0 ? C + 1 : C;
-        if (ry.mw == (T)0 || wb <= tz0 || wb >= tz1) return 0x7fffffff;
+        if (ry.mw == (T)0 || wb <= tzl || wb >= tzh) return 0x7fffffff;
         const T qf = ceil(fabs((T)wb - ry.w0) * ry.imw) - (T)(la + 1);   // (wb - w0)/mw
         return max((int)fmin(qf, (T)1e9), lo);
       };
@@ -1491,12 +1530,12 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       if constexpr (Z3) {
         const T iLa = (T)1 / ry.La;
         auto visit3 = [&](int ia, int ib, int iw, T h) {
-          deposit(8 * ((iw - tz0) * TXY + (ia - la) * sa + (ib - lbb) * sbs), h * iLa);
+          deposit(8 * ((iw - tzl) * TXY + (ia - la) * sa + (ib - lbb) * sbs), h * iLa);
         };
         while (rest != 0u) {
           const int q = __ffs(rest) - 1;
           rest &= rest - 1u;
-          walk_row<T, true, true>(ry, la + q, lbb, hb, tz0, tz1, visit3);
+          walk_row<T, true, true>(ry, la + q, lbb, hb, tzl, tzh, visit3);
         }
       }
     }

@@ -73,9 +73,11 @@ def test_iterate_os_full_fan512_one_epoch(orc):
     c = torch.tensor(inp["c0"], device=DEV)
     plan.iterate_os(c, torch.tensor(inp["d"], device=DEV), torch.tensor(mask, device=DEV), inp["Z"],
                     8, 1)
-    e = rel(c.cpu().numpy(), ref)
-    print(f"fan512 mixed S=8, 1 epoch: image rel {e:.3e}")
-    assert e <= 1e-5
+    # eight updates of the image: relative L2 1e-5, element-wise the image
+    # bound 1e-4
+    e2, em = rel_l2(c.cpu().numpy(), ref), rel_max(c.cpu().numpy(), ref)
+    print(f"fan512 mixed S=8, 1 epoch: image rel L2 {e2:.3e}, max-abs/max {em:.3e}")
+    assert e2 <= 1e-5 and em <= 1e-4
 
 
 def test_iterate_os_rejects_bad_subsets():
