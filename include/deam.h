@@ -177,6 +177,19 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
                    int32_t mode, const void* v, void* w, void* g, double* obj, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* deam_poly_mean for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments without the workspace, the same results bit for bit.
+ * Its scratch (the per-block objective partials and the weight maxima) is a
+ * fixed device array of the library, 2 MiB per GPU, held until the process
+ * ends; it serves at most 67 100 672 rays (R larger returns
+ * DEAM_ERR_UNSUPPORTED, enqueuing nothing).  The call allocates nothing and
+ * records no memset.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (different streams, or host threads) race. */
+int deam_poly_mean_noalloc(const deam_plan* plan, const void* l, const float* d,
+                           const uint8_t* mask, int32_t mode, const void* v, void* w, void* g,
+                           double* obj, void* stream);
+
 /* Backprojection with the transpose of the system operator of Eq. 8 (the
  * same h(x,y) as deam_forward): b[c][x] = sum_y h(x,y) w[c][y].  With the
  * DEAM weights of deam_poly_mean it gives b~_i and b^_i of the component

@@ -29,7 +29,8 @@ EXPORTS = ("deam_plan_create", "deam_plan_destroy", "deam_plan_sizes", "deam_wor
            "deam_penalty", "deam_update_penalized", "deam_iterate_penalized",
            "deam_fbp", "deam_nmar", "deam_mar_init", "deam_iterate_os", "deam_dual_workspace_size",
            "deam_iterate_dual", "deam_dilate_mask", "deam_plan_set_bowtie", "deam_pack_mask",
-           "deam_iterate_packed", "deam_iterate_sync", "deam_validate_inputs", "deam_last_error")
+           "deam_iterate_packed", "deam_iterate_sync", "deam_validate_inputs", "deam_poly_mean_noalloc",
+           "deam_last_error")
 
 
 class DeamGeometry(C.Structure):
@@ -75,6 +76,7 @@ def load():
         "deam_metal_trace": [vp, vp, dp, vp, vp, vp, sz, vp],
         "deam_forward": [vp, vp, i32, vp, vp, sz, vp],
         "deam_poly_mean": [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp],
+        "deam_poly_mean_noalloc": [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp],
         "deam_backproject": [vp, vp, i32, i32, vp, vp, sz, vp],
         "deam_update": [vp, vp, vp, vp, vp, vp],
         "deam_iterate": [vp, vp, vp, vp, vp, vp, i32, vp, vp, sz, vp],

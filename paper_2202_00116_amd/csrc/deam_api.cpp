@@ -455,6 +455,8 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     p->mu_eff_inv[1][0] = -c * id;
     p->mu_eff_inv[1][1] = a * id;
   }
+  // the no-allocation scratch of this device (looked up once per device)
+  if (deam::noalloc_scratch(&p->noalloc) != hipSuccess) p->noalloc = nullptr;
   p->h1_bound = h1_bound(g);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
   *out = p;
@@ -588,6 +590,42 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
                                        : deam::PM_STEP;
   uint32_t* wmax = (uint32_t*)(wsb + L.wmax);
   double* partial = (double*)(wsb + L.partial);
+  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
+  if (obj) HIP_TRY(deam::launch_reduce(partial, plan->ray_blocks, obj, st));
+  return ok();
+}
+
+int deam_poly_mean_noalloc(const deam_plan* plan, const void* l, const float* d,
+                           const uint8_t* mask, int32_t mode, const void* v, void* w, void* g,
+                           double* obj, void* stream) {
+  if (int rc = check_plan(plan)) return rc;
+  if (!l || !w) return fail(DEAM_ERR_NULL, "l or w is NULL");
+  if (mode != DEAM_W_AM && mode != DEAM_W_GRAD && mode != DEAM_W_VJP && mode != DEAM_W_STEP_VJP)
+    return fail(DEAM_ERR_VALUE, "unknown weight mode %d", mode);
+  if ((mode == DEAM_W_VJP || mode == DEAM_W_STEP_VJP) && !v)
+    return fail(DEAM_ERR_NULL, "v is NULL in VJP mode");
+  if (mode != DEAM_W_VJP && !d) return fail(DEAM_ERR_NULL, "d is NULL");
+  const size_t need = deam::kNoAllocPartialOffset + (size_t)plan->ray_blocks * sizeof(double);
+  if (need > deam::kNoAllocScratchBytes)
+    return fail(DEAM_ERR_UNSUPPORTED,
+                "%lld rays need %zu bytes of scratch, more than the %zu of deam_poly_mean_noalloc "
+                "(at most %lld rays); use deam_poly_mean with a workspace",
+                (long long)plan->gd.R, need, deam::kNoAllocScratchBytes,
+                (long long)((deam::kNoAllocScratchBytes - deam::kNoAllocPartialOffset) /
+                            sizeof(double) * deam::kFpBlock));
+  if (!plan->noalloc)
+    return fail(DEAM_ERR_HIP, "the device scratch of deam_poly_mean_noalloc is not available");
+  hipStream_t st = (hipStream_t)stream;
+  const int pm = mode == DEAM_W_AM     ? deam::PM_AM
+                 : mode == DEAM_W_GRAD ? deam::PM_GRAD
+                 : mode == DEAM_W_VJP  ? deam::PM_VJP
+                                       : deam::PM_STEP;
+  char* s = (char*)plan->noalloc;
+  uint32_t* wmax = (uint32_t*)s;
+  double* partial = (double*)(s + deam::kNoAllocPartialOffset);
+  // the maxima start at zero (a fill kernel, no memset node); the kernel
+  // writes every partial it reduces
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
   HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
   if (obj) HIP_TRY(deam::launch_reduce(partial, plan->ray_blocks, obj, st));

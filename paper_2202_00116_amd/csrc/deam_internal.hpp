@@ -110,6 +110,12 @@ inline int64_t fp3_blocks(int n_views, int n_rows, int n_cols, int rg) {
 constexpr int kViewBatch = 128;
 constexpr int kMaxFbpCols = 4096;   // FBP filter: one detector row of p and g in LDS (64 KiB)
 
+// Device scratch of deam_poly_mean_noalloc (a file-scope array of the kernel
+// library, one copy per GPU): 256 bytes of per-channel weight maxima, then
+// the FP64 per-block partial sums of the objective.
+constexpr size_t kNoAllocScratchBytes = (size_t)2 << 20;
+constexpr size_t kNoAllocPartialOffset = 256;
+
 // Elements of the zeroed tail that follows the two packed image copies.  The
 // lanes of a forward-projector wave walk a common range of plane rows q <
 // max(nx, ny), so a lane whose row lies outside the slices (3D) reads the
@@ -165,6 +171,7 @@ struct deam_plan {
   double i0sum[2];
   double mu_eff[2][2];
   double mu_eff_inv[2][2];
+  void* noalloc;                 // device address of the no-allocation scratch (NULL if unavailable)
 };
 
 namespace deam {
@@ -229,5 +236,10 @@ hipError_t launch_validate(const deam_plan* p, const double* c64, const float* d
                            unsigned long long* cnt, hipStream_t st);
 
 WsLayout workspace_layout(const deam_plan* p, int op);
+
+// Device address of the no-allocation scratch on the current device, looked
+// up once per device (hipGetSymbolAddress) and cached; the host-side name of
+// the array is not a device address.
+hipError_t noalloc_scratch(void** ptr);
 
 }  // namespace deam

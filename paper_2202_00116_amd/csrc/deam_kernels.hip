@@ -29,7 +29,12 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
+
+// Scratch of deam_poly_mean_noalloc: every call on a GPU uses that GPU's
+// copy, so calls that overlap on one GPU race.
+static __device__ __align__(256) unsigned char scratch[deam::kNoAllocScratchBytes];
 
 namespace deam {
 namespace {
@@ -2524,6 +2529,25 @@ hipError_t launch_validate(const deam_plan* p, const double* c64, const float* d
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, st, c64, nc, d, nd, cnt);
   return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_pack_mask(const deam_plan* p, const uint8_t* mask, uint32_t* bits,
