@@ -186,6 +186,11 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
     L.cp_y = take((2 * V + tail) * es);
     L.cp_x = L.cp_y + V * es;
   };
+  // the weight-maxima map and the per-tile maxima of the backprojector
+  auto take_bp_maps = [&]() {
+    L.wmap = take((size_t)wmap_words(p->gd) * 4);
+    L.tmax = take((size_t)max_tiles(p->gd) * 4 * sizeof(float));
+  };
   switch (op) {
     case DEAM_OP_FORWARD:
       take_packed(2 * rs);
@@ -200,6 +205,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       break;
     case DEAM_OP_BACKPROJECT:
       L.wmax = take(64);
+      take_bp_maps();
       break;
     case DEAM_OP_ITERATE_VJP:
       take_packed(2 * rs);
@@ -212,6 +218,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.bl = take(V * 2 * rs);
       L.partial = take((size_t)p->ray_blocks * 8);
       L.wmax = take(64);
+      take_bp_maps();
       break;
     case DEAM_OP_PENALTY:
       L.partial = take((size_t)pen_blocks(p) * 8);
@@ -225,6 +232,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.partial = take((nblk + (size_t)pen_blocks(p)) * 8);
       L.wmax = take(64);
       L.scratch = take(64);
+      take_bp_maps();
       break;
     case DEAM_OP_FBP:
       L.q = take(R * 2 * rs);
@@ -247,6 +255,7 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.partial = take(nblk * 8);
       L.wmax = take(64);
       L.scratch = take(64);
+      take_bp_maps();
       break;
   }
   L.total = off;
@@ -642,10 +651,11 @@ int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, int32_t
   deam::WsLayout L;
   if (int rc = check_ws(plan, DEAM_OP_BACKPROJECT, ws, ws_bytes, L)) return rc;
   hipStream_t st = (hipStream_t)stream;
-  uint32_t* wmax = (uint32_t*)((char*)ws + L.wmax);
-  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-  HIP_TRY(deam::launch_absmax(plan, w, n_ch, wmax, st));
-  HIP_TRY(deam::launch_backproject(plan, w, n_ch, (flags & DEAM_BP_NONNEG) != 0, wmax, b, st));
+  uint32_t* wmap = (uint32_t*)((char*)ws + L.wmap);
+  float* tmax = (float*)((char*)ws + L.tmax);
+  HIP_TRY(deam::launch_absmax(plan, w, n_ch, wmap, st));
+  HIP_TRY(deam::launch_backproject(plan, w, n_ch, (flags & DEAM_BP_NONNEG) != 0, wmap, tmax, b,
+                                   st));
   return ok();
 }
 
@@ -721,6 +731,9 @@ static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const 
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
   uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  uint32_t* wmap = (uint32_t*)(w + L.wmap);
+  float* tmax = (float*)(w + L.tmax);
+  const int64_t nmap = deam::wmap_words(plan->gd);
   double* partial = (double*)(w + L.partial);
   // events: per iteration, before/after the ray kernel, before/after the
   // backprojection, after the update
@@ -755,8 +768,10 @@ static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const 
   STEP(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
     STEP(deam::launch_fill_u32(wmax, 0u, 16, st));
+    STEP(deam::launch_fill_u32(wmap, 0u, nmap, st));
     STEP(mark(k, 0));
-    STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
+    STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st,
+                              wmap));
     STEP(mark(k, 1));
     if (obj_hist) {
       int64_t np = plan->fp_blocks;
@@ -767,7 +782,7 @@ static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const 
       STEP(deam::launch_reduce(partial, np, obj_hist + k, st));
     }
     STEP(mark(k, 2));
-    STEP(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
+    STEP(deam::launch_backproject(plan, w + L.w, 4, true, wmap, tmax, w + L.b, st));
     STEP(mark(k, 3));
     void* cp_out = k == n_iter - 1 ? c_proj : nullptr;   // the final iterate's copy
     if (pen) {
@@ -999,6 +1014,9 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
   uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  uint32_t* wmap = (uint32_t*)(w + L.wmap);
+  float* tmax = (float*)(w + L.tmax);
+  const int64_t nmap = deam::wmap_words(plan->gd);
   double* partial = (double*)(w + L.partial);
   HIP_TRY(deam::launch_update(plan, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
   HIP_TRY(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
@@ -1011,8 +1029,10 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
     for (int s = 0; s < n_sub; ++s) {
       const deam_plan sub = subset_plan(plan, n_sub, s);
       HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-      HIP_TRY(deam::launch_fp_poly(&sub, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
-      HIP_TRY(deam::launch_backproject(&sub, w + L.w, 4, true, wmax, w + L.b, st));
+      HIP_TRY(deam::launch_fill_u32(wmap, 0u, nmap, st));
+      HIP_TRY(deam::launch_fp_poly(&sub, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st,
+                                   wmap));
+      HIP_TRY(deam::launch_backproject(&sub, w + L.w, 4, true, wmap, tmax, w + L.b, st));
       HIP_TRY(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
     }
   }
@@ -1065,6 +1085,10 @@ int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double
   void* cpx = wa + LA.cp_x;
   uint32_t* wmax_a = (uint32_t*)(wa + LA.wmax);
   uint32_t* wmax_b = (uint32_t*)(wb + LB.wmax);
+  uint32_t* wmap_a = (uint32_t*)(wa + LA.wmap);
+  uint32_t* wmap_b = (uint32_t*)(wb + LB.wmap);
+  float* tmax_a = (float*)(wa + LA.tmax);
+  float* tmax_b = (float*)(wb + LB.tmax);
   double* part_a = (double*)(wa + LA.partial);
   double* part_b = (double*)(wb + LB.partial);
   double* two = (double*)(wa + LA.scratch);
@@ -1073,17 +1097,19 @@ int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double
   for (int k = 0; k < n_iter; ++k) {
     HIP_TRY(deam::launch_fill_u32(wmax_a, 0u, 16, st));
     HIP_TRY(deam::launch_fill_u32(wmax_b, 0u, 16, st));
+    HIP_TRY(deam::launch_fill_u32(wmap_a, 0u, deam::wmap_words(plan_lo->gd), st));
+    HIP_TRY(deam::launch_fill_u32(wmap_b, 0u, deam::wmap_words(plan_hi->gd), st));
     HIP_TRY(deam::launch_fp_poly(plan_lo, cpy, cpx, d_lo, mask_lo, deam::PM_AM, wa + LA.w, part_a,
-                                 wmax_a, st));
+                                 wmax_a, st, wmap_a));
     HIP_TRY(deam::launch_fp_poly(plan_hi, cpy, cpx, d_hi, mask_hi, deam::PM_AM, wb + LB.w, part_b,
-                                 wmax_b, st));
+                                 wmax_b, st, wmap_b));
     if (obj_hist) {
       HIP_TRY(deam::launch_reduce(part_a, plan_lo->fp_blocks, two, st));
       HIP_TRY(deam::launch_reduce(part_b, plan_hi->fp_blocks, two + 1, st));
       HIP_TRY(deam::launch_reduce(two, 2, obj_hist + k, st));
     }
-    HIP_TRY(deam::launch_backproject(plan_lo, wa + LA.w, 4, true, wmax_a, wa + LA.b, st));
-    HIP_TRY(deam::launch_backproject(plan_hi, wb + LB.w, 4, true, wmax_b, wb + LB.b, st));
+    HIP_TRY(deam::launch_backproject(plan_lo, wa + LA.w, 4, true, wmap_a, tmax_a, wa + LA.b, st));
+    HIP_TRY(deam::launch_backproject(plan_hi, wb + LB.w, 4, true, wmap_b, tmax_b, wb + LB.b, st));
     HIP_TRY(deam::launch_update(plan_lo, c64, wa + LA.b, Z[0], Z[1], nullptr, cpy, cpx, st,
                                 wb + LB.b));
   }
@@ -1108,6 +1134,8 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
   uint32_t* wmax = (uint32_t*)(w + L.wmax);
+  uint32_t* wmap = (uint32_t*)(w + L.wmap);
+  float* tmax = (float*)(w + L.tmax);
   double* partial = (double*)(w + L.partial);
   // forward pass of the iteration, recomputed: l = H c, weights, b = H^T w
   HIP_TRY(deam::launch_update(plan, const_cast<double*>(c64), nullptr, Z[0], Z[1], nullptr, cpy,
@@ -1115,9 +1143,10 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   HIP_TRY(deam::launch_zero_tail(plan, cpx, dbl, st));
   HIP_TRY(deam::launch_forward(plan, cpy, cpx, w + L.l, 2, st));
   HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
+  HIP_TRY(deam::launch_fill_u32(wmap, 0u, deam::wmap_words(plan->gd), st));
   HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_AM, nullptr, w + L.w, nullptr,
-                            partial, wmax, st));
-  HIP_TRY(deam::launch_backproject(plan, w + L.w, 4, true, wmax, w + L.b, st));
+                            partial, wmax, st, wmap));
+  HIP_TRY(deam::launch_backproject(plan, w + L.w, 4, true, wmap, tmax, w + L.b, st));
   // upstream images for b~ and b^, and their projections alpha = H u~, beta = H u^
   HIP_TRY(deam::launch_step_u(plan, G, w + L.b, Z[0], Z[1], w + L.u, st));
   for (int p = 0; p < 2; ++p) {
@@ -1127,9 +1156,8 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   // lambda per ray, then out = G + H^T lambda
   HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_STEP, w + L.ab, w + L.lam, nullptr,
                             partial, nullptr, st));
-  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-  HIP_TRY(deam::launch_absmax(plan, w + L.lam, 2, wmax, st));
-  HIP_TRY(deam::launch_backproject(plan, w + L.lam, 2, false, wmax, w + L.bl, st));
+  HIP_TRY(deam::launch_absmax(plan, w + L.lam, 2, wmap, st));
+  HIP_TRY(deam::launch_backproject(plan, w + L.lam, 2, false, wmap, tmax, w + L.bl, st));
   HIP_TRY(deam::launch_add_g(plan, G, w + L.bl, out, st));
   return ok();
 }

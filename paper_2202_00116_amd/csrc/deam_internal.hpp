@@ -73,17 +73,23 @@ struct Tiling {
 // two tiles share a CU.
 // Threads per tile: 1024 in 2D (a whole CU, 16 waves), 256 for SM tiles (four
 // per CU); 512 in 3D (two tiles per CU).
-template <bool Z3, bool SM>
-constexpr int bp_block() { return Z3 ? 512 : (SM ? 256 : 1024); }
+#ifndef DEAM_BP3_PK_TZ
+#define DEAM_BP3_PK_TZ 1
+#endif
+#ifndef DEAM_BP3_PK_BLOCK
+#define DEAM_BP3_PK_BLOCK 512
+#endif
+template <bool Z3, bool SM, bool PK = false>
+constexpr int bp_block() { return Z3 ? (PK ? DEAM_BP3_PK_BLOCK : 512) : (SM ? 256 : 1024); }
 
 template <bool Z3, int NCH, bool PK, bool SM>
 struct BpTile {
   static_assert(!(Z3 && SM), "small tiles are 2D only");
-  static constexpr int block = bp_block<Z3, SM>();
+  static constexpr int block = bp_block<Z3, SM, PK>();
   static constexpr int wpv = PK ? NCH / 2 : NCH;   // 64-bit LDS words per voxel
   static constexpr int tx = SM ? 16 : 32;
   static constexpr int ty = SM ? 16 : 32;
-  static constexpr int tz = Z3 ? (PK ? 2 : 8 / NCH) : 1;
+  static constexpr int tz = Z3 ? (PK ? DEAM_BP3_PK_TZ : 8 / NCH) : 1;
   static constexpr size_t lds_bytes = (size_t)(tx + 1) * ty * tz * wpv * 8;
   static_assert(lds_bytes <= 81920, "backprojection tile exceeds 80 KiB");
 };
@@ -128,6 +134,35 @@ inline size_t packed_tail_elems(int nx, int ny) {
   return mx * mx + 2;
 }
 
+// Coarse map of the weight maxima: max |w_c| over the rays of one view,
+// one group of kMapRows detector rows and one block of kMapCols channels,
+// per channel c < 4, as float bits (non-negative, so atomicMax on the bits
+// is the float maximum).  Written by the kernels that produce weights, read
+// by the backprojector's tile pre-pass, which takes each tile's maximum over
+// the entries of the rays that can meet it: the fixed-point scale of a tile
+// then follows the weights of its own rays, not the largest weight of the
+// scan.
+constexpr int kMapRows = 4;
+constexpr int kMapCols = 64;
+struct WMapDev {
+  uint32_t* map;        // [n_views][ngm][nkb][4], or NULL (no map)
+  int n_rows, n_cols;
+  int ngm, nkb;         // row groups, channel blocks
+};
+inline WMapDev wmap_dev(const GeomDev& G, void* map) {
+  return WMapDev{(uint32_t*)map, G.n_rows, G.n_cols, (G.n_rows + kMapRows - 1) / kMapRows,
+                 (G.n_cols + kMapCols - 1) / kMapCols};
+}
+inline int64_t wmap_words(const GeomDev& G) {
+  const WMapDev M = wmap_dev(G, nullptr);
+  return (int64_t)G.n_views * M.ngm * M.nkb * 4;
+}
+// An upper bound of the backprojector's tile count over its tile shapes
+// (per-tile maxima, 4 floats each).
+inline int64_t max_tiles(const GeomDev& G) {
+  return (int64_t)((G.nx + 15) / 16) * ((G.ny + 15) / 16) * (G.is3d ? G.nz : 1);
+}
+
 // Workspace pieces (byte offsets, 256-aligned).
 struct WsLayout {
   size_t cp_y, cp_x;     // packed projection images (natural and transposed)
@@ -135,6 +170,7 @@ struct WsLayout {
   size_t b;              // back-projections
   size_t partial;        // per-block FP64 partial sums
   size_t wmax;           // per-channel max |w| (uint32 float bits)
+  size_t wmap, tmax;     // weight-maxima map and per-tile maxima (backprojection)
   size_t scratch;        // small FP64 scratch
   size_t l, u, ab, lam, bl;   // iteration VJP: line integrals, upstream images, their
                               // projections, lambda, its backprojection
@@ -184,18 +220,22 @@ hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x
                           int n_out, hipStream_t st);
 hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* cp_x, double t,
                               uint8_t* mask, double* T, hipStream_t st);
+// wmap (or NULL): the weight-maxima map, which must hold zeros before
 hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
                           const uint8_t* mask, int mode, void* w, double* partial,
-                          uint32_t* wmax, hipStream_t st);
+                          uint32_t* wmax, hipStream_t st, uint32_t* wmap = nullptr);
 hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
                        int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
-                       hipStream_t st);
+                       hipStream_t st, uint32_t* wmap = nullptr);
 hipError_t launch_reduce(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
-hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmax, hipStream_t st);
-// nonneg: every weight is >= 0 (the AM weights), which allows a cheaper rounding
+// the weight-maxima map of w (zeroed here first)
+hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmap, hipStream_t st);
+// nonneg: every weight is >= 0 (the AM weights), which allows a cheaper rounding.
+// wmap: the weights' map (from the kernel that wrote them or launch_absmax);
+// tmax: per-tile maxima, max_tiles(G) x 4 floats of scratch
 hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
-                              const uint32_t* wmax, void* b, hipStream_t st);
+                              const uint32_t* wmap, float* tmax, void* b, hipStream_t st);
 // iteration VJP: u = (-G_i/(Z_i b~_i), ..., G_i/(Z_i b^_i)) planar [4][V]
 hipError_t launch_step_u(const deam_plan* p, const double* G, const void* b, double z1, double z2,
                          void* u, hipStream_t st);

@@ -36,6 +36,10 @@
 // copy, so calls that overlap on one GPU race.
 static __device__ __align__(256) unsigned char scratch[deam::kNoAllocScratchBytes];
 
+#ifndef DEAM_BP_INCREMENTAL
+#define DEAM_BP_INCREMENTAL 1
+#endif
+
 namespace deam {
 namespace {
 
@@ -137,10 +141,10 @@ struct Ray {
 // Returns false if the ray misses the box.  Lateral pixel indices of the
 // walk (and the lateral bounds given to walk_row) are relative to ry.ib, and
 // in 3D slice indices (and the axial bounds) relative to ry.iw, the slice at
-// the middle of the ray's driving range; the axial line is set up in FP64
-// from the FP64 ray table, so that its rounding, and with it the error of a
-// slice crossing (that rounding divided by |mw|, which is small for rays
-// close to the slice planes), is set by the axial distance travelled.
+// the middle of the ray's driving range, so that the rounding of the axial
+// coordinate, and with it the error of a slice crossing (that rounding
+// divided by |mw|, which is small for rays close to the slice planes), is
+// set by the axial distance travelled and not by the volume's height.
 template <typename T>
 __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __restrict__ rays,
                                          int v, int r, int k, int lox, int loy, int loz, int hix,
@@ -152,13 +156,16 @@ __device__ __forceinline__ bool make_ray(const GeomDev& G, const RayXY<T>* __res
   T mw = 0, w0 = (T)0.5, rmw = 0;
   int iw = 0;
   if (G.is3d) {
-    const RayXY<double>& t64 = G.rays64[(int64_t)v * G.n_cols + k];
-    const double mw64 = G.row[4 * r] * t64.ida;
-    const double w064 = G.view[4 * v + 3] - t64.sa * mw64;        // w at a = 0
-    const double amid = 0.5 * (yd ? G.ny : G.nx);
-    iw = (int)floor(fmin(fmax(fma(amid, mw64, w064), -1e6), 1e6));
-    mw = (T)mw64;
-    w0 = (T)(w064 - (double)iw);
+    // w(a) = w_s + (a - s_a) mw: w_s (the source's slice coordinate) enters
+    // relative to iw through one FP64 subtraction, so no rounding of a
+    // coordinate as large as the volume is left
+    const T zr = (T)G.row[4 * r];
+    mw = zr * t.ida;
+    const double ws = G.view[4 * v + 3];
+    const T pz = zr * (t.sa * t.ida);                  // w_s - w(0)
+    const T amid = (T)(0.5 * (yd ? G.ny : G.nx));
+    iw = ifloor(clampf(fma(amid, mw, (T)ws - pz), (T)-1e6, (T)1e6));
+    w0 = (T)(ws - (double)iw) - pz;
     rmw = mw != (T)0 ? (T)1 / mw : (T)0;
   }
   const T alo_box = (T)(yd ? loy : lox), ahi_box = (T)(yd ? hiy : hix);
@@ -702,11 +709,45 @@ __device__ void poly_epilogue(const EBin<T>* __restrict__ eb, int nE, T l1, T l2
   }
 }
 
+// Weight-maxima map: the lanes of the wave with the same entry (a view, a
+// group of rows, a block of channels) take the maximum of their |w_c| and one
+// of them raises the entry with atomicMax on the float bits (non-negative).
+// A wave's lanes map to at most a few entries; all 64 lanes must call this.
+__device__ __forceinline__ void map_update(const WMapDev& M, int64_t entry, const float m[4],
+                                           int nch, bool valid) {
+  if (!M.map) return;
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(valid);
+  while (todo) {
+    const int src = __ffsll(todo) - 1;
+    const int lo = __shfl((int)(entry & 0xffffffff), src), hi = __shfl((int)(entry >> 32), src);
+    const int64_t e0 = ((int64_t)hi << 32) | (uint32_t)lo;
+    const bool sel = valid && entry == e0;
+    float mx[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mx[c] = sel ? m[c] : 0.f;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx[c] = fmaxf(mx[c], __shfl_xor(mx[c], o));
+    }
+    if (lane == src)
+      for (int c = 0; c < nch; ++c) atomicMax(&M.map[e0 * 4 + c], __float_as_uint(mx[c]));
+    todo &= ~__ballot(sel);
+  }
+}
+
+__device__ __forceinline__ int64_t map_entry(const WMapDev& M, int v, int r, int k) {
+  return ((int64_t)v * M.ngm + r / kMapRows) * M.nkb + k / kMapCols;
+}
+
 // Block reductions: FP64 sum into partial[lb], float max into wmax (atomicMax
-// on the bit pattern, valid for non-negative values).
+// on the bit pattern, valid for non-negative values), and the map entry of
+// each lane's ray.
 template <int NW, int NT = kFpBlock>
 __device__ void block_reduce(double term, const float wabs[4], int nch, double* partial, int lb,
-                             uint32_t* wmax) {
+                             uint32_t* wmax, const WMapDev& M = WMapDev{}, int64_t entry = 0,
+                             bool valid = false) {
+  map_update(M, entry, wabs, nch, valid);
   __shared__ double s_sum[NT / 64];
   __shared__ float s_max[NT / 64][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -745,7 +786,7 @@ __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof
     const EBin<T>* __restrict__ eb, int nE,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
     double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
-    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
+    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout, WMapDev M) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   // rays of the walked views, channel fastest; `ray` is the index in the
   // full sinogram
@@ -753,11 +794,13 @@ __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof
   const bool active = lray < (int64_t)G.nvl * G.n_rows * G.n_cols;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
+  int64_t entry = 0;
   {
     const int64_t ra = active ? lray : 0;
     const int k = (int)(ra % G.n_cols);
     const int rv = (int)(ra / G.n_cols);
     const int r = rv % G.n_rows, v = G.voff + G.vsub * (rv / G.n_rows);
+    entry = map_entry(M, v, r, k);
     const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
     T l1, l2;
     const RayXY<T>* rays = (sizeof(T) == 8) ? (const RayXY<T>*)G.rays64 : (const RayXY<T>*)G.rays;
@@ -782,7 +825,7 @@ __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof
   }
   if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
     const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
-    block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax);
+    block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax, M, entry, active);
   }
 }
 
@@ -811,7 +854,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
     const EBin<T>* __restrict__ eb, int nE,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
     double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
-    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout) {
+    uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout, WMapDev M) {
   using T2 = typename Vec2<T>::type;
   constexpr uint32_t E = sizeof(T2);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -1073,7 +1116,10 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
   }
   if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
     const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
-    block_reduce<4, 64 * kFp3Views>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax);
+    // the lane's rows r0 .. r0 + RG - 1 lie in one group of the map (RG divides it)
+    static_assert(kMapRows % RG == 0, "row groups of the map hold whole row groups of the walk");
+    block_reduce<4, 64 * kFp3Views>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax, M,
+                                     map_entry(M, v, r0, k), valid);
   }
 }
 
@@ -1082,7 +1128,7 @@ __global__ __launch_bounds__(kFpBlock) void k_poly(
     int64_t R, const EBin<T>* __restrict__ eb, int nE, const T* __restrict__ l,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, const T* __restrict__ v,
     T* __restrict__ w, T* __restrict__ gout, double* __restrict__ partial,
-    uint32_t* __restrict__ wmax, int n_cols, const T* __restrict__ bt) {
+    uint32_t* __restrict__ wmax, int n_cols, const T* __restrict__ bt, WMapDev M) {
   const int64_t ray = (int64_t)blockIdx.x * kFpBlock + threadIdx.x;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
@@ -1096,19 +1142,26 @@ __global__ __launch_bounds__(kFpBlock) void k_poly(
     poly_epilogue<T, MODE>(eb, nE, l1, l2, ray, R, d, mask, v, w, gout, term, wabs);
   }
   const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
-  block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, wmax);
+  const int64_t rr = ray < R ? ray : 0;
+  const int64_t vr = rr / M.n_cols;
+  const int64_t entry =
+      map_entry(M, (int)(vr / M.n_rows), (int)(vr % M.n_rows), (int)(rr % M.n_cols));
+  block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, wmax, M, entry, ray < R);
 }
 
 // max |w_c| over rays, per channel (for the fixed-point scale of a
 // backprojection of arbitrary weights).
 template <typename T>
 __global__ __launch_bounds__(kFpBlock) void k_absmax(int64_t R, int nch, const T* __restrict__ w,
-                                                     uint32_t* __restrict__ wmax) {
+                                                     WMapDev M) {
+  const int64_t ray = (int64_t)blockIdx.x * kFpBlock + threadIdx.x;
   float m[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t i = (int64_t)blockIdx.x * kFpBlock + threadIdx.x; i < R;
-       i += (int64_t)gridDim.x * kFpBlock)
-    for (int c = 0; c < nch; ++c) m[c] = fmaxf(m[c], (float)fabs(w[c * R + i]));
-  block_reduce<4>(0.0, m, nch, nullptr, 0, wmax);
+  const int64_t rr = ray < R ? ray : 0;
+  if (ray < R)
+    for (int c = 0; c < nch; ++c) m[c] = (float)fabs(w[c * R + ray]);
+  const int64_t vr = rr / M.n_cols;
+  map_update(M, map_entry(M, (int)(vr / M.n_rows), (int)(vr % M.n_rows), (int)(rr % M.n_cols)),
+             m, nch, ray < R);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -1180,6 +1233,32 @@ __device__ __forceinline__ unsigned long long to_fixed_nonneg(double x) {
 // whose rays can meet its slices, from its z-range and its distance to the
 // source; s_off receives the exclusive prefix sum of the work items per view,
 // nk * ceil(nr / RG).
+// Channel coordinate (fractional channel index) of the ray of view v through
+// the point (px, py) (mm).
+__device__ __forceinline__ float channel_coord(const GeomDev& G, int v, double px, double py) {
+  const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
+  const double qx = px - G.sid * cb, qy = py - G.sid * sb;
+  const float cr = (float)(-cb * qy + sb * qx), dt = (float)(-cb * qx - sb * qy);
+  return atan2f(cr, dt) / (float)G.dgamma + (float)G.kc;
+}
+
+// Detector rows [rl, rh] of view v whose rays can meet the slab [Z0, Z1] of
+// the box [X0, X1] x [Y0, Y1] (3D; from its distance to the source).
+__device__ __forceinline__ void slab_rows(const GeomDev& G, int v, double X0, double X1, double Y0,
+                                          double Y1, double Z0, double Z1, int& rl, int& rh) {
+  const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
+  const double zs = G.view[4 * v + 2];
+  const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
+  const double dmin = fmax(sqrt((sx - cx) * (sx - cx) + (sy - cy) * (sy - cy)), 1e-6);
+  const double fx = fmax(fabs(sx - X0), fabs(sx - X1)), fy = fmax(fabs(sy - Y0), fabs(sy - Y1));
+  const double dmax = sqrt(fx * fx + fy * fy);
+  const double za = (Z0 - zs) * G.sdd, zb = (Z1 - zs) * G.sdd;
+  const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
+  const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
+  rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
+  rh = min(ifloor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
+}
+
 template <int RG, int VB>
 __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0, double X1,
                                            double Y0, double Y1, double Z0, double Z1,
@@ -1190,13 +1269,7 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
     const int j = i >> 2, cn = i & 3;
     const int v = G.voff + G.vsub * (vb0 + j);
     float kap = 0.f;
-    if (vb0 + j < G.nvl) {
-      const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
-      const double px = (cn & 1) ? X1 : X0, py = (cn & 2) ? Y1 : Y0;
-      const double qx = px - G.sid * cb, qy = py - G.sid * sb;
-      const float cr = (float)(-cb * qy + sb * qx), dt = (float)(-cb * qx - sb * qy);
-      kap = atan2f(cr, dt) / (float)G.dgamma + (float)G.kc;
-    }
+    if (vb0 + j < G.nvl) kap = channel_coord(G, v, (cn & 1) ? X1 : X0, (cn & 2) ? Y1 : Y0);
     s_kap[j][cn] = kap;
   }
   __syncthreads();
@@ -1211,17 +1284,8 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
       const int kh = min((int)floorf(kmx + 0.01f), G.n_cols - 1);
       nk = max(kh - kl + 1, 0);
       if (G.is3d) {
-        const double sx = G.sid * G.view[4 * v], sy = G.sid * G.view[4 * v + 1];
-        const double zs = G.view[4 * v + 2];
-        const double cx = fmin(fmax(sx, X0), X1), cy = fmin(fmax(sy, Y0), Y1);
-        const double dmin = fmax(sqrt((sx - cx) * (sx - cx) + (sy - cy) * (sy - cy)), 1e-6);
-        const double fx = fmax(fabs(sx - X0), fabs(sx - X1)), fy = fmax(fabs(sy - Y0), fabs(sy - Y1));
-        const double dmax = sqrt(fx * fx + fy * fy);
-        const double za = (Z0 - zs) * G.sdd, zb = (Z1 - zs) * G.sdd;
-        const double q0 = za / dmin, q1 = za / dmax, q2 = zb / dmin, q3 = zb / dmax;
-        const double zmn = fmin(fmin(q0, q1), fmin(q2, q3)), zmx = fmax(fmax(q0, q1), fmax(q2, q3));
-        rl = max((int)ceil(zmn / G.dzeta + G.rc - 1e-3), 0);
-        const int rh = min(ifloor(zmx / G.dzeta + G.rc + 1e-3), G.n_rows - 1);
+        int rh;
+        slab_rows(G, v, X0, X1, Y0, Y1, Z0, Z1, rl, rh);
         nr = max(rh - rl + 1, 0);
       } else {
         nr = 1;
@@ -1254,6 +1318,63 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
   __syncthreads();
 }
 
+// Weight bound of every backprojector tile: the largest |w_c| (c < nch) over
+// the map entries of the rays that can meet the tile, one block per tile
+// (the tile index is the backprojector's logical one).  The channel and row
+// ranges are those of cull_views widened by one, so they hold every ray the
+// tile walks.
+__global__ __launch_bounds__(256) void k_tile_max(GeomDev G, Tiling TL, WMapDev M, int nch,
+                                                  float* __restrict__ tmax) {
+  const int t = blockIdx.x;
+  const int tix = t % TL.ntx, tiy = (t / TL.ntx) % TL.nty, tiz = t / (TL.ntx * TL.nty);
+  const int tx0 = tix * TL.tx, ty0 = tiy * TL.ty, tz0 = tiz * TL.tz;
+  const int tx1 = min(tx0 + TL.tx, G.nx), ty1 = min(ty0 + TL.ty, G.ny);
+  const int tz1 = min(tz0 + TL.tz, G.is3d ? G.nz : 1);
+  const double X0 = G.x0 + tx0 * G.dx, X1 = G.x0 + tx1 * G.dx;
+  const double Y0 = G.y0 + ty0 * G.dy, Y1 = G.y0 + ty1 * G.dy;
+  const double Z0 = G.z0 + tz0 * G.dz, Z1 = G.z0 + tz1 * G.dz;
+  uint32_t m[4] = {0u, 0u, 0u, 0u};
+  for (int i = threadIdx.x; i < G.nvl; i += 256) {
+    const int v = G.voff + G.vsub * i;
+    float kmn = 1e30f, kmx = -1e30f;
+#pragma unroll
+    for (int cn = 0; cn < 4; ++cn) {
+      const float kap = channel_coord(G, v, (cn & 1) ? X1 : X0, (cn & 2) ? Y1 : Y0);
+      kmn = fminf(kmn, kap);
+      kmx = fmaxf(kmx, kap);
+    }
+    const int kl = max((int)ceilf(kmn - 0.01f) - 1, 0);
+    const int kh = min((int)floorf(kmx + 0.01f) + 1, G.n_cols - 1);
+    int rl = 0, rh = 0;
+    if (G.is3d) {
+      slab_rows(G, v, X0, X1, Y0, Y1, Z0, Z1, rl, rh);
+      rl = max(rl - 1, 0);
+      rh = min(rh + 1, G.n_rows - 1);
+    }
+    if (kl > kh || rl > rh) continue;
+    for (int gr = rl / kMapRows; gr <= rh / kMapRows; ++gr)
+      for (int kb = kl / kMapCols; kb <= kh / kMapCols; ++kb) {
+        const uint32_t* e = M.map + (((int64_t)v * M.ngm + gr) * M.nkb + kb) * 4;
+        for (int c = 0; c < nch; ++c) m[c] = max(m[c], e[c]);
+      }
+  }
+  // block maximum (bit patterns of non-negative floats order as the floats)
+  __shared__ uint32_t s_m[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m[c] = max(m[c], (uint32_t)__shfl_xor((int)m[c], o));
+    if (lane == 0) s_m[wv][c] = m[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = threadIdx.x;
+    const uint32_t x = max(max(s_m[0][c], s_m[1][c]), max(s_m[2][c], s_m[3][c]));
+    tmax[(int64_t)t * 4 + c] = __uint_as_float(x);
+  }
+}
+
 // One backprojector for both geometries.  A workgroup owns a tile of
 // BpTile<Z3, NCH, PK, SM> voxels in LDS and scatters every ray that meets it, view
 // batch by view batch; work items are (view, detector row, channel) with the
@@ -1269,8 +1390,8 @@ __device__ __forceinline__ void cull_views(const GeomDev& G, int vb0, double X0,
 // afterwards through the general walk_row, so that the lanes of a wave stay
 // on the common path.
 template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
-__global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
-                                                 const uint32_t* __restrict__ wmax, double h1,
+__global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH == 4>())) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
+                                                 const float* __restrict__ tmax, double h1,
                                                  double hmax, T* __restrict__ b) {
   // Packed accumulation (float plans, the 4 non-negative AM channels): the
   // LDS word of a voxel holds two channels as 32-bit halves, so one atomic
@@ -1311,12 +1432,14 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
   for (int o = 0; o < 2 * NOWN; ++o) tot[o] = 0ull;
 
   // h1 bounds max_x sum_y h(x,y) over all views (n_views times a per-view
-  // bound); a batch of VB views contributes at most VB / n_views of it
+  // bound); a batch of VB views contributes at most VB / n_views of it.  The
+  // weight bound m is the tile's own (k_tile_max): the largest |w_c| of the
+  // rays that can meet the tile
   const double hb = h1 * (double)min(VB, G.nvl) / (double)G.n_views;
   T scl[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const float m = __uint_as_float(wmax[c]);
+    const float m = tmax[(int64_t)t * 4 + c];
     double s;
     if (PK)   // 2^32 - 2^20: room for the rounding of every term
       s = (m > 0.f && hb > 0.0) ? 4293918720.0 / (hb * (double)m) : 0.0;
@@ -1496,6 +1619,38 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
       };
       // a full step [fa, fa + 1] inside one slice (DEP), or one that crosses
       // a slice plane and only advances the in-plane state (!DEP)
+#if DEAM_BP_INCREMENTAL
+      // Full steps in Siddon's incremental form: e is the distance (in plane
+      // spacings) from the start of the step to the next lateral plane.  A
+      // step with e < 1 splits there and moves one pixel in the direction sg,
+      // and e grows by 1/|mb| - 1, otherwise it falls by 1 (exact).  Only the
+      // crossings round, so over the at most 32 steps of a chord in the tile
+      // e stays within a few ulp of the line's value.  (The clamp keeps a
+      // split at the tile's lateral face, within rounding of the chord's end,
+      // in the tile.)
+      const int sg = ry.mb > (T)0 ? 1 : (ry.mb < (T)0 ? -1 : 0);
+      const T iab = fabs(ry.imb), iab1 = iab - (T)1;
+      T e = (T)0;
+      auto fstep = [&](auto dep) {
+        fa += (T)1;
+        const bool cr = e < (T)1;
+        const int B = clampi(A + (cr ? sg : 0), lbb, hb - 1);
+        if constexpr (decltype(dep)::value) {
+          const T dA = clamp0(e, (T)1);
+          QT qa[NCH];
+          quant(dA, qa);
+          add(__mul24(A, sb8) + row8, qa);
+          if (cr) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) qa[c] = LQ[c] - qa[c];
+            add(__mul24(B, sb8) + row8, qa);
+          }
+        }
+        e += cr ? iab1 : (T)-1;
+        row8 += 8 * sa;
+        A = B;
+      };
+#else
       auto fstep = [&](auto dep) {
         fa += (T)1;
         const T bn = fma(fa, ry.mb, ry.b0);
@@ -1515,10 +1670,16 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
         A = B;
         bp = bn;
       };
+#endif
       if (q0 < q1) {
         gstep(q0);
         const int ql = q1 - 1;     // the last step (partial) is gstep's
         int q = q0 + 1;
+#if DEAM_BP_INCREMENTAL
+        // the distance to the next lateral plane from the line at the start
+        // of the first full step
+        e = sg > 0 ? ((T)(A + 1) - bp) * iab : (sg < 0 ? (bp - (T)A) * iab : (T)1e30);
+#endif
         while (q < ql) {
           // full steps up to the next slice crossing, then the crossing step
           const int qe = min(qc, ql);
@@ -1530,6 +1691,11 @@ __global__ __launch_bounds__((bp_block<Z3, SM>())) __attribute__((amdgpu_waves_p
           }
         }
         tp = fa;   // the last step starts on a plane
+#if DEAM_BP_INCREMENTAL
+        // back to the line for the last (partial) step
+        bp = fma(fa, ry.mb, ry.b0);
+        A = clampi(ifloor(bp), lbb, hb - 1);
+#endif
         if (ql > q0) gstep(ql);
       }
       if constexpr (Z3) {
@@ -2169,8 +2335,10 @@ hipError_t launch_zero_tail(const deam_plan* p, void* cp_x, bool dbl, hipStream_
 template <typename T, int MODE>
 static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
                         const uint8_t* mask, void* out, double* partial, uint32_t* wmax,
-                        double tthr, uint8_t* mask_out, double* Tout, hipStream_t st, int nout = 2) {
+                        double tthr, uint8_t* mask_out, double* Tout, hipStream_t st, int nout = 2,
+                        uint32_t* wmap = nullptr) {
   using T2 = typename Vec2<T>::type;
+  const WMapDev M = wmap_dev(p->gd, wmap);
   const dim3 grid((unsigned)p->ray_blocks), blk(kFpBlock);
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
   // the x-major copy follows the natural one in the same allocation
@@ -2180,10 +2348,10 @@ static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, 
     const dim3 grid3((unsigned)fp3_blocks(p->gd.nvl, p->gd.n_rows, p->gd.n_cols, RG));
     hipLaunchKernelGGL((k_fp3<T, MODE, RG>), grid3, dim3(64 * kFp3Views), 0, st, p->gd,
                        (const T2*)cp_y, xoff,
-                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
+                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout, M);
   } else
     hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
-                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout);
+                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout, M);
 }
 
 hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
@@ -2206,14 +2374,14 @@ hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* 
 
 hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
                           const uint8_t* mask, int mode, void* w, double* partial,
-                          uint32_t* wmax, hipStream_t st) {
+                          uint32_t* wmax, hipStream_t st, uint32_t* wmap) {
   const bool dbl = p->precision == DEAM_PREC_FP64;
   if (mode == PM_AM) {
-    if (dbl) fp_dispatch<double, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
-    else fp_dispatch<float, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+    if (dbl) fp_dispatch<double, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
+    else fp_dispatch<float, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
   } else if (mode == PM_GRAD) {
-    if (dbl) fp_dispatch<double, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
-    else fp_dispatch<float, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st);
+    if (dbl) fp_dispatch<double, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
+    else fp_dispatch<float, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
   } else {
     return hipErrorInvalidValue;
   }
@@ -2223,35 +2391,36 @@ hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x
 template <typename T>
 static void poly_dispatch(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
                           int mode, const void* v, void* w, void* g, double* partial,
-                          uint32_t* wmax, hipStream_t st) {
+                          uint32_t* wmax, hipStream_t st, uint32_t* wmap) {
   const int64_t R = p->gd.R;
+  const WMapDev M = wmap_dev(p->gd, wmap);
   const dim3 grid((unsigned)((R + kFpBlock - 1) / kFpBlock)), blk(kFpBlock);
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
   if (mode == PM_AM)
     hipLaunchKernelGGL((k_poly<T, PM_AM>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
                        (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
-                       (const T*)p->gd.bowtie);
+                       (const T*)p->gd.bowtie, M);
   else if (mode == PM_GRAD)
     hipLaunchKernelGGL((k_poly<T, PM_GRAD>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d,
                        mask, (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
-                       (const T*)p->gd.bowtie);
+                       (const T*)p->gd.bowtie, M);
   else if (mode == PM_VJP)
     hipLaunchKernelGGL((k_poly<T, PM_VJP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
                        (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
-                       (const T*)p->gd.bowtie);
+                       (const T*)p->gd.bowtie, M);
   else
     hipLaunchKernelGGL((k_poly<T, PM_STEP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
                        (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
-                       (const T*)p->gd.bowtie);
+                       (const T*)p->gd.bowtie, M);
 }
 
 hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
                        int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
-                       hipStream_t st) {
+                       hipStream_t st, uint32_t* wmap) {
   if (p->precision == DEAM_PREC_FP64)
-    poly_dispatch<double>(p, l, d, mask, mode, v, w, g, partial, wmax, st);
+    poly_dispatch<double>(p, l, d, mask, mode, v, w, g, partial, wmax, st, wmap);
   else
-    poly_dispatch<float>(p, l, d, mask, mode, v, w, g, partial, wmax, st);
+    poly_dispatch<float>(p, l, d, mask, mode, v, w, g, partial, wmax, st, wmap);
   return hipGetLastError();
 }
 
@@ -2265,22 +2434,25 @@ hipError_t launch_fill_u32(uint32_t* ptr, uint32_t v, int64_t n, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmax,
+hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmap,
                          hipStream_t st) {
   const int64_t R = p->gd.R;
-  const unsigned nb = (unsigned)std::min<int64_t>((R + kFpBlock - 1) / kFpBlock, 2048);
+  hipError_t e = launch_fill_u32(wmap, 0u, wmap_words(p->gd), st);
+  if (e != hipSuccess) return e;
+  const WMapDev M = wmap_dev(p->gd, wmap);
+  const unsigned nb = (unsigned)((R + kFpBlock - 1) / kFpBlock);
   if (p->precision == DEAM_PREC_FP64)
     hipLaunchKernelGGL(k_absmax<double>, dim3(nb), dim3(kFpBlock), 0, st, R, n_ch,
-                       (const double*)w, wmax);
+                       (const double*)w, M);
   else
     hipLaunchKernelGGL(k_absmax<float>, dim3(nb), dim3(kFpBlock), 0, st, R, n_ch,
-                       (const float*)w, wmax);
+                       (const float*)w, M);
   return hipGetLastError();
 }
 
 template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
-static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
-                           hipStream_t st) {
+static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wmap, float* tmax,
+                           void* b, hipStream_t st) {
   using BT = BpTile<Z3, NCH, NONNEG && sizeof(T) == 4 && NCH == 4, SM>;
   Tiling TL{BT::tx, BT::ty, BT::tz, 0, 0, 0};
   TL.ntx = (p->gd.nx + BT::tx - 1) / BT::tx;
@@ -2288,49 +2460,53 @@ static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wm
   TL.ntz = ((Z3 ? p->gd.nz : 1) + BT::tz - 1) / BT::tz;
   const size_t lds = BT::lds_bytes;
   const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
-  auto kern = k_bp<T, Z3, NCH, NONNEG, SM>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  if ((int64_t)nt > max_tiles(p->gd)) return hipErrorInvalidValue;   // tmax holds max_tiles
+  hipLaunchKernelGGL(k_tile_max, dim3(nt), dim3(256), 0, st, p->gd, TL,
+                     wmap_dev(p->gd, const_cast<uint32_t*>(wmap)), NCH, tmax);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nt), dim3(BT::block), lds, st, p->gd, TL, (const T*)w, wmax,
-                     p->h1_bound, p->hmax, (T*)b);
+  auto kern = k_bp<T, Z3, NCH, NONNEG, SM>;
+  e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nt), dim3(BT::block), lds, st, p->gd, TL, (const T*)w,
+                     (const float*)tmax, p->h1_bound, p->hmax, (T*)b);
   return hipGetLastError();
 }
 
 // 2D: whole-CU 32 x 32 tiles when there are enough of them to give every
 // compute unit one, else 16 x 16 tiles (four per CU)
 template <typename T, bool Z3, int NCH, bool NONNEG>
-static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmax, void* b,
-                        hipStream_t st) {
+static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmap, float* tmax,
+                        void* b, hipStream_t st) {
   if constexpr (Z3) {
-    return bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmax, b, st);
+    return bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st);
   } else {
     const int64_t n32 = (int64_t)((p->gd.nx + 31) / 32) * ((p->gd.ny + 31) / 32);
-    return n32 >= p->n_cu ? bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmax, b, st)
-                          : bp_tiles<T, Z3, NCH, NONNEG, true>(p, w, wmax, b, st);
+    return n32 >= p->n_cu ? bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st)
+                          : bp_tiles<T, Z3, NCH, NONNEG, true>(p, w, wmap, tmax, b, st);
   }
 }
 
 template <typename T, bool Z3>
 static hipError_t bp_by_channels(const deam_plan* p, const void* w, int n_ch, bool nonneg,
-                                 const uint32_t* wmax, void* b, hipStream_t st) {
+                                 const uint32_t* wmap, float* tmax, void* b, hipStream_t st) {
   switch (n_ch) {
-    case 1: return bp_go<T, Z3, 1, false>(p, w, wmax, b, st);
-    case 2: return bp_go<T, Z3, 2, false>(p, w, wmax, b, st);
+    case 1: return bp_go<T, Z3, 1, false>(p, w, wmap, tmax, b, st);
+    case 2: return bp_go<T, Z3, 2, false>(p, w, wmap, tmax, b, st);
     case 4:
-      return nonneg ? bp_go<T, Z3, 4, true>(p, w, wmax, b, st)
-                    : bp_go<T, Z3, 4, false>(p, w, wmax, b, st);
+      return nonneg ? bp_go<T, Z3, 4, true>(p, w, wmap, tmax, b, st)
+                    : bp_go<T, Z3, 4, false>(p, w, wmap, tmax, b, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
-                              const uint32_t* wmax, void* b, hipStream_t st) {
+                              const uint32_t* wmap, float* tmax, void* b, hipStream_t st) {
   if (p->precision == DEAM_PREC_FP64)
-    return p->gd.is3d ? bp_by_channels<double, true>(p, w, n_ch, nonneg, wmax, b, st)
-                      : bp_by_channels<double, false>(p, w, n_ch, nonneg, wmax, b, st);
-  return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, nonneg, wmax, b, st)
-                    : bp_by_channels<float, false>(p, w, n_ch, nonneg, wmax, b, st);
+    return p->gd.is3d ? bp_by_channels<double, true>(p, w, n_ch, nonneg, wmap, tmax, b, st)
+                      : bp_by_channels<double, false>(p, w, n_ch, nonneg, wmap, tmax, b, st);
+  return p->gd.is3d ? bp_by_channels<float, true>(p, w, n_ch, nonneg, wmap, tmax, b, st)
+                    : bp_by_channels<float, false>(p, w, n_ch, nonneg, wmap, tmax, b, st);
 }
 
 hipError_t launch_step_u(const deam_plan* p, const double* G, const void* b, double z1, double z2,
