@@ -227,7 +227,8 @@ def helical_oracle_iterates(helical):
     """The oracle's iterates c^0, c^1, ... and objectives F(c^0), ..., grown on
     demand one iteration at a time (an iteration is deterministic, so
     iterating from c^k once gives c^(k+1))."""
-    return {"c": [helical["c0"]], "h": [], "resolved": [np.ones(helical["c0"].shape[1], bool)]}
+    return {"c": [helical["c0"]], "h": [], "resolved": [np.ones(helical["c0"].shape[1], bool)],
+            "level": [np.full(helical["c0"].shape[1], np.inf)]}
 
 
 def oracle_iterate_to(orc, inp, mask_o, state, k):
@@ -237,12 +238,14 @@ def oracle_iterate_to(orc, inp, mask_o, state, k):
         c, h, b = orc.iterate(inp["geom"], inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"],
                               state["c"][-1], 1, want_b=True)
         bh = b[2:]
-        ok = np.all(bh >= RESOLVED * bh.max(axis=1, keepdims=True), axis=0)
+        lev = (bh / bh.max(axis=1, keepdims=True)).min(axis=0)   # b^ relative to its maximum
+        ok = lev >= RESOLVED
         state["c"].append(c)
         state["h"].append(float(h[0]))
         state["resolved"].append(state["resolved"][-1] & ok)
+        state["level"].append(np.minimum(state["level"][-1], lev))
         print(f"oracle helical iteration {len(state['c']) - 1}: {time.time() - t0:.1f} s", flush=True)
-    return state["c"][k], np.array(state["h"][:k]), state["resolved"][k]
+    return state["c"][k], np.array(state["h"][:k]), state["resolved"][k], state["level"][k]
 
 
 @pytest.mark.parametrize("k,prec,tol,htol", [(1, "mixed", 1e-4, 1e-6), (1, "fp64", 1e-10, 1e-10),
@@ -256,7 +259,7 @@ def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_or
     from paper_2202_00116_amd.plan import Plan
     inp = helical
     mask_o, _ = helical_trace
-    c_o, h_o, resolved = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, k)
+    c_o, h_o, resolved, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, k)
     plan = Plan(inp["geom"], inp["I0"], inp["mu"], prec)
     c = torch.tensor(inp["c0"], device=DEV)
     hist = torch.zeros(k, dtype=torch.float64, device=DEV)
@@ -265,6 +268,12 @@ def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_or
     eh = float(np.abs(hist.cpu().numpy() - h_o).max() / h_o[0])
     print(f"helical {prec} after {k} iterations: objective rel {eh:.3e}")
     c = c.cpu().numpy()
+    err = np.abs(c - c_o).max(axis=0) / np.abs(c_o).max()
+    for lo, hi in ((0, 1e-10), (1e-10, 1e-8), (1e-8, 1e-6), (1e-6, 1e-4), (1e-4, np.inf)):
+        sel = (level > lo) & (level <= hi)
+        if sel.any():
+            print(f"  b^/max in ({lo:.0e}, {hi:.0e}]: {int(sel.sum())} voxels, max error "
+                  f"{err[sel].max():.3e} of max|c|")
     rest = np.abs(c - c_o)[:, ~resolved]
     print(f"helical {prec}: {int((~resolved).sum())} of {resolved.size} voxels with b^ below "
           f"{RESOLVED} of its maximum (max error there {rest.max(initial=0.0) / np.abs(c_o).max():.3e}"
