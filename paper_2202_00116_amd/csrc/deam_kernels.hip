@@ -2130,7 +2130,11 @@ __global__ __launch_bounds__(256) void k_fbp_filter(int n_cols, int64_t R, const
 // pixel: f(x) = (2 pi / n_views) sum_v Q_v(gamma') / L^2, where gamma' and L are
 // the fan angle and the distance of the pixel centre seen from the source of
 // view v, and Q_v is interpolated linearly between channels (zero outside the
-// detector).  Geometry in the plan precision, sums in FP64.
+// detector).  Geometry, interpolation and sums in FP64 in both precisions: the
+// channel coordinate is a few hundred channels, so in FP32 its rounding alone
+// (up to 6e-5 channel) would move the interpolation by that fraction of the
+// jump between neighbouring channels, which next to metal is most of the
+// image's range.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fbp_bp(GeomDev G, int n_ch, const T* __restrict__ Q,
                                                 double scale, T* __restrict__ img) {
@@ -2138,28 +2142,29 @@ __global__ __launch_bounds__(256) void k_fbp_bp(GeomDev G, int n_ch, const T* __
   const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (x >= V) return;
   const int ix = (int)(x % G.nx), iy = (int)(x / G.nx);
-  const T px = (T)(G.x0 + (ix + 0.5) * G.dx), py = (T)(G.y0 + (iy + 0.5) * G.dy);
-  const T sid = (T)G.sid, ida = (T)(1.0 / G.dgamma), kc = (T)G.kc;
+  const double px = G.x0 + (ix + 0.5) * G.dx, py = G.y0 + (iy + 0.5) * G.dy;
+  const double ida = 1.0 / G.dgamma;
   const int n = G.n_cols;
   const int64_t R = G.R;
   double acc0 = 0.0, acc1 = 0.0;
   for (int v = 0; v < G.n_views; ++v) {
-    const T cb = (T)G.view[4 * v], sb = (T)G.view[4 * v + 1];
-    const T vx = px - sid * cb, vy = py - sid * sb;
+    const double cb = G.view[4 * v], sb = G.view[4 * v + 1];
+    const double vx = px - G.sid * cb, vy = py - G.sid * sb;
     // central ray u = -(cos b, sin b): cross(u, v) and dot(u, v)
-    const T gam = atan2(sb * vx - cb * vy, -(cb * vx + sb * vy));
-    const T L2 = vx * vx + vy * vy;
-    const T kf = gam * ida + kc;
-    const T fk = floor(kf);
+    const double gam = atan2(sb * vx - cb * vy, -(cb * vx + sb * vy));
+    const double L2 = vx * vx + vy * vy;
+    const double kf = gam * ida + G.kc;
+    const double fk = floor(kf);
     const int k0 = (int)fk;
     if (k0 < -1 || k0 > n - 1) continue;
-    const T fr = kf - fk;
+    const double fr = kf - fk;
     const int64_t r0 = (int64_t)v * n + k0;
-    const T q00 = k0 >= 0 ? Q[r0] : (T)0, q01 = k0 + 1 < n ? Q[r0 + 1] : (T)0;
-    acc0 += (double)(((T)1 - fr) * q00 + fr * q01) / (double)L2;
+    const double q00 = k0 >= 0 ? (double)Q[r0] : 0.0, q01 = k0 + 1 < n ? (double)Q[r0 + 1] : 0.0;
+    acc0 += ((1.0 - fr) * q00 + fr * q01) / L2;
     if (n_ch > 1) {
-      const T q10 = k0 >= 0 ? Q[R + r0] : (T)0, q11 = k0 + 1 < n ? Q[R + r0 + 1] : (T)0;
-      acc1 += (double)(((T)1 - fr) * q10 + fr * q11) / (double)L2;
+      const double q10 = k0 >= 0 ? (double)Q[R + r0] : 0.0;
+      const double q11 = k0 + 1 < n ? (double)Q[R + r0 + 1] : 0.0;
+      acc1 += ((1.0 - fr) * q10 + fr * q11) / L2;
     }
   }
   img[x] = (T)(scale * acc0);

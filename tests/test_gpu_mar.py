@@ -15,11 +15,18 @@ from tests.errors import rel_l2, rel_max
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-# FP32 plans place a pixel on the detector with an FP32 channel coordinate
-# (|k| <= 2 n_cols): its rounding, ~2^-24 * 2 n_cols (1e-4 channel at 816
-# channels), times the largest channel-to-channel step of the filtered test
-# sinogram (<= its maximum) bounds the error relative to the image maximum.
-TOL = {"mixed": 1e-4, "fp64": 1e-12}
+# The FBP backprojection places pixels on the detector and sums in FP64 in
+# both precisions; FP32 plans round only the stored filtered sinogram and the
+# image (2^-24 relative each).  The ramp-filtered terms partly cancel in the
+# sum over views, which amplifies the first rounding relative to the image:
+# 16 units of 2^-24 of the image maximum leave room for a cancellation ratio
+# of about 8 (measured errors are below 1 unit).
+TOL = {"mixed": 1e-6, "fp64": 1e-12}
+# The whole initialisation in FP32 plans also takes FP32 line integrals, the
+# FP32 projection of the prior, NMAR and the Eq. 4 decomposition; the
+# threshold decisions are compared where the oracle's value is not within
+# 1e-5 of the threshold.
+TOL_INIT = {"mixed": 2e-5, "fp64": 1e-10}
 
 
 @pytest.fixture(scope="module")
@@ -103,7 +110,7 @@ def test_mar_init_matches_oracle(mo, name, prec):
     # precision's rounding of the threshold
     thr = prm["metal_frac"] * prm["water"][1]
     margin = np.abs(ref["mu0"][1] - thr) / thr
-    sure = margin > (1e-4 if prec == "mixed" else 1e-10)
+    sure = margin > (1e-5 if prec == "mixed" else 1e-10)
     print(f"{name} {prec}: min metal-threshold margin {margin.min():.2e}, "
           f"{int((~sure).sum())} undecided voxels")
     assert np.array_equal(M[sure], ref["M"][sure])
@@ -112,7 +119,7 @@ def test_mar_init_matches_oracle(mo, name, prec):
     e = max(rel_l2(c, ref["c"]), rel_max(c, ref["c"]))
     print(f"{name} {prec}: c rel err (L2 and element-wise) {e:.3e}, metal voxels {int(M.sum())}, "
           f"trace rays {int(mask.sum())}")
-    assert e <= (5e-4 if prec == "mixed" else 1e-10)
+    assert e <= TOL_INIT[prec]
 
 
 def test_mar_init_rejects_helical_plan():
@@ -126,7 +133,7 @@ def test_mar_init_rejects_helical_plan():
                       mar_params(inp["geom"], inp["I0"]))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 2e-5)])
 def test_deam_from_mar_initialisation(mo, prec, tol):
     """The 128 x 128 workload as its configuration states it: the MAR
     initialisation supplies c^0 and the metal trace, then 20 DEAM iterations;
@@ -194,5 +201,5 @@ def test_mar_init_without_metal(mo, prec):
     c, M, mask = plan.mar_init(torch.tensor(d, device=DEV), prm)
     assert int(M.sum()) == 0 and int(mask.sum()) == 0
     e = max(rel_l2(c.cpu().numpy(), ref["c"]), rel_max(c.cpu().numpy(), ref["c"]))
-    assert e <= (5e-4 if prec == "mixed" else 1e-10), e
+    assert e <= TOL_INIT[prec], e
     assert np.allclose(mo.decompose(ref["mu0"], inp["I0"], inp["mu"]), ref["c"], rtol=1e-12, atol=1e-14)
