@@ -207,18 +207,17 @@ def test_helical_mask_all_rays(helical, helical_trace):
     assert mask_o.sum() > 0
 
 
-# The packed fixed-point backprojection quantises every term against the
-# largest weight of its view batch, over all rays.  At the cold start the
-# estimated weights w^ of the rays that the starting image attenuates along a
-# whole water disk are 5 orders of magnitude below those of rays that miss
-# it; voxels at the two ends of the helix are seen only by such rays, and
-# their estimated backprojection b^ is then 1e-10 to 1e-6 of its maximum,
-# a few quanta (FP32 path) or a few units of 2^-61 of the maximum (FP64
-# path).  Their update, the log of a ratio of such numbers, is not resolved.
-# Both bounds are asserted on the voxels whose b^_1 and b^_2 (in every
-# iteration compared) are at least RESOLVED times their maximum; the others
-# are counted and reported, and over all voxels a relative L2 ten times the
-# bound is asserted.
+# The packed fixed-point backprojection quantises every term in units of
+# 2^-32 of a bound for one view batch: the largest weight of the rays that can
+# meet the voxel's tile times a bound of one batch's sum of intersection
+# lengths.  Voxels at the two ends of the helix are reached only by the ends
+# of a few chords at the edge of the cone, so their estimated backprojection
+# b^ is 1e-10 to 1e-6 of its maximum: a few quanta (FP32 path) or a few units
+# of 2^-61 of the bound (FP64 path).  Their update, the log of a ratio of such
+# numbers, is not resolved.  Both bounds are asserted on the voxels whose
+# b^_1 and b^_2 (in every iteration compared) are at least RESOLVED times
+# their maximum; the others are counted and reported, and over all voxels a
+# relative L2 ten times the bound is asserted.
 RESOLVED = 1e-6
 
 

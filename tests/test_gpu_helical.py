@@ -115,8 +115,9 @@ def test_packed_backprojection_weakest_voxels(orc, name):
     four channels), on the DEAM weights at the cold start, against the
     oracle: over the whole image and on the 1 % of seen voxels with the
     smallest backprojections, element by element relative to each voxel's own
-    value (the fixed-point resolution is set by the largest weight of a view
-    batch, so it is coarsest there)."""
+    value (the fixed-point resolution is set per tile by the largest weight of
+    the rays that can meet it, so relative to a voxel's own sum it is coarsest
+    there)."""
     from paper_2202_00116_amd.plan import Plan
     inp = make_inputs(name)
     g = inp["geom"]
