@@ -284,3 +284,40 @@ def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_or
     assert eh <= htol
     del plan
     torch.cuda.empty_cache()
+
+
+def test_helical_mixed_tracks_fp64_over_30_iterations(orc, helical, helical_trace,
+                                                     helical_oracle_iterates):
+    """The workload's 30 iterations: mixed precision against the all-FP64 GPU
+    path (itself checked against the oracle above), over the voxels the
+    oracle resolves in its first iteration, with the error reported per band
+    of the oracle's b^ level; the objective histories agree."""
+    from paper_2202_00116_amd.plan import Plan
+    inp = helical
+    mask_o, _ = helical_trace
+    _, _, resolved, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, 1)
+    n = 30
+    d = torch.tensor(inp["d"], device=DEV)
+    mask = torch.tensor(mask_o, device=DEV)
+    out, hist = {}, {}
+    for prec in ("mixed", "fp64"):
+        plan = Plan(inp["geom"], inp["I0"], inp["mu"], prec)
+        c = torch.tensor(inp["c0"], device=DEV)
+        h = torch.zeros(n, dtype=torch.float64, device=DEV)
+        plan.iterate(c, d, mask, inp["Z"], n, h)
+        out[prec], hist[prec] = c.cpu().numpy(), h.cpu().numpy()
+        del plan
+        torch.cuda.empty_cache()
+    c, c64 = out["mixed"], out["fp64"]
+    err = np.abs(c - c64).max(axis=0) / np.abs(c64).max()
+    for lo, hi in ((1e-6, 1e-4), (1e-4, np.inf)):
+        sel = (level > lo) & (level <= hi)
+        print(f"  b^/max in ({lo:.0e}, {hi:.0e}]: {int(sel.sum())} voxels, max error "
+              f"{err[sel].max():.3e} of max|c|")
+    eh = float(np.abs(hist["mixed"] - hist["fp64"]).max() / hist["fp64"][0])
+    print(f"helical {n} iterations mixed vs fp64: objective rel {eh:.3e}, decrease "
+          f"{hist['fp64'][0]:.6e} -> {hist['fp64'][-1]:.6e}")
+    assert np.all(np.diff(hist["fp64"]) < 0)
+    assert eh <= 1e-6
+    assert_close(c[:, resolved], c64[:, resolved], 1e-4,
+                 what=f"helical {n} iterations mixed vs fp64 (resolved voxels)")
