@@ -201,7 +201,11 @@ int deam_poly_mean_noalloc(const deam_plan* plan, const void* l, const float* d,
  *   accumulation of deam_iterate (two channels per LDS word).  A negative
  *   weight under DEAM_BP_NONNEG gives undefined results.
  * Accumulation is exact integer (fixed point) per voxel, so results are
- * bitwise reproducible.  Workspace: deam_workspace_size(DEAM_OP_BACKPROJECT). */
+ * bitwise reproducible.  Each term is rounded to a quantum set per image
+ * tile by the largest |w| among the rays that can meet the tile (the call
+ * finds these maxima from w), so the relative resolution of a voxel's sum
+ * follows the weights of its own rays.
+ * Workspace: deam_workspace_size(DEAM_OP_BACKPROJECT). */
 enum { DEAM_BP_NONNEG = 1 };
 int deam_backproject(const deam_plan* plan, const void* w, int32_t n_ch, int32_t flags, void* b,
                      void* ws, size_t ws_bytes, void* stream);

@@ -1188,7 +1188,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ p, i
 // Backprojection: tile-owned, fixed point in LDS
 // ---------------------------------------------------------------------------
 // Fixed point: one signed 64-bit word per voxel and channel holding the sum
-// of round(h * w_c * s_c).
+// of round(h * w_c * s_c).  max|w_c| below is the tile's own bound: the
+// largest |w_c| of the rays that can meet the tile (k_tile_max).
 //  * FP32 plans: s_c = (2^31 - 2^8) / (hmax * max|w_c|), hmax = the voxel
 //    diagonal (no segment is longer), so every term fits a signed 32-bit
 //    integer and converts with one instruction; the resolution is 2^-31 of
