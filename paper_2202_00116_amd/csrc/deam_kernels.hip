@@ -1496,12 +1496,16 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
       const int k = s_kl[j] + ((Z3 || kk < nh) ? (Z3 ? kk : 2 * kk) : 2 * (kk - nh) + 1);
       const int r = s_rl[j] + rr;
       const int v = G.voff + G.vsub * (vb0 + j);
-      Ray<T> ry;
-      if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
+      // the weights are loaded before the ray set-up, which does not need
+      // them, so that the two loads' latencies overlap
       const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
       T wa[NCH];   // weight x scale x mm per unit of the driving axis
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) wa[c] = w[c * G.R + ray] * scl[c] * ry.La;
+      for (int c = 0; c < NCH; ++c) wa[c] = w[c * G.R + ray];
+      Ray<T> ry;
+      if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) wa[c] = wa[c] * scl[c] * ry.La;
       const bool yd = ry.ydrive != 0;
       const int la = yd ? ty0 : tx0;
       // the tile's lateral range in the ray's frame (pixels relative to ry.ib)
