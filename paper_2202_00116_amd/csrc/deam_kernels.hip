@@ -1190,12 +1190,14 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ p, i
 // Fixed point: one signed 64-bit word per voxel and channel holding the sum
 // of round(h * w_c * s_c).  max|w_c| below is the tile's own bound: the
 // largest |w_c| of the rays that can meet the tile (k_tile_max).
-//  * FP32 plans: s_c = (2^31 - 2^8) / (hmax * max|w_c|), hmax = the voxel
+//  * FP32 plans: s_c = (2^31 - 2^11) / (hmax * max|w_c|), hmax = the voxel
 //    diagonal (no segment is longer), so every term fits a signed 32-bit
-//    integer and converts with one instruction; the resolution is 2^-31 of
-//    the largest possible term, below the FP32 rounding of the product for
-//    all but terms 2^8 times smaller than the largest, and sums of up to 2^32
-//    terms cannot overflow 64 bits.
+//    integer and converts with one instruction: the FP32 roundings of s_c,
+//    of w_c s_c L_a and of the final product (at most 4 units of 2^-24)
+//    raise the largest term by at most 2^31 * 2^-22 = 512 < 2^11.  The
+//    resolution is 2^-31 of the largest possible term, below the FP32
+//    rounding of the product for all but terms 2^8 times smaller than the
+//    largest, and sums of up to 2^32 terms cannot overflow 64 bits.
 //  * FP64 plans: s_c = 2^61 / (h1 * max|w_c|), h1 >= max_x sum_y h(x,y), so
 //    every partial sum stays below 2^61 + (number of additions)/2 < 2^63; a
 //    term (< 2^52) is split exactly into two 32-bit halves.
@@ -1442,10 +1444,11 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
   for (int c = 0; c < NCH; ++c) {
     const float m = tmax[(int64_t)t * 4 + c];
     double s;
-    if (PK)   // 2^32 - 2^20: room for the rounding of every term
+    if (PK)   // 2^32 - 2^20: room for the +1/2 of every term's rounding and for the FP32
+              // roundings of the scaled weights (at most 2^-22 of the bound, 1024)
       s = (m > 0.f && hb > 0.0) ? 4293918720.0 / (hb * (double)m) : 0.0;
     else if (sizeof(T) == 4)
-      s = (m > 0.f && hmax > 0.0) ? 2147483392.0 / (hmax * (double)m) : 0.0;
+      s = (m > 0.f && hmax > 0.0) ? 2147481600.0 / (hmax * (double)m) : 0.0;
     else
       s = (m > 0.f && h1 > 0.0) ? 2305843009213693952.0 / (h1 * (double)m) : 0.0;
     // FP64, non-negative: every term (at most hmax * max|w| * s) below 2^51
