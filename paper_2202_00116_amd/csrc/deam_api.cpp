@@ -53,7 +53,8 @@ int check_plan(const deam_plan* p) {
 
 // Upper bound of max_x sum_y h(x,y): per view at most nk channels and nr rows
 // pass through one voxel, each with a chord no longer than the voxel diagonal.
-double h1_bound(const deam_geometry& g) {
+// rays (optional): nk * nr, the bound of the rays of one view through a voxel.
+double h1_bound(const deam_geometry& g, double* rays = nullptr) {
   const bool is3d = g.kind == DEAM_HELICAL3D;
   const double rc = 0.5 * std::hypot(g.nx * g.dx, g.ny * g.dy);
   const double dmin = g.sid - rc;
@@ -68,6 +69,7 @@ double h1_bound(const deam_geometry& g) {
     nr = std::min<double>(std::floor(width / dzeta) + 2.0, g.n_rows);
     diag = std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz);
   }
+  if (rays) *rays = std::min<double>(nk, g.n_cols) * nr;
   return (double)g.n_views * std::min<double>(nk, g.n_cols) * nr * diag;
 }
 
@@ -401,6 +403,7 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
     if (p->d_energy) (void)hipFree(p->d_energy);
     if (p->d_rays) (void)hipFree(p->d_rays);
     if (p->d_rays64) (void)hipFree(p->d_rays64);
+    if (p->d_hbt) (void)hipFree(p->d_hbt);
     delete p;
   };
   if (hipMalloc(&p->d_tables, tab.size() * sizeof(double)) != hipSuccess ||
@@ -466,8 +469,21 @@ int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* 
   }
   // the no-allocation scratch of this device (looked up once per device)
   if (deam::noalloc_scratch(&p->noalloc) != hipSuccess) p->noalloc = nullptr;
-  p->h1_bound = h1_bound(g);
+  p->h1_bound = h1_bound(g, &p->bp_rays_per_voxel);
   p->hmax = is3d ? std::sqrt(g.dx * g.dx + g.dy * g.dy + g.dz * g.dz) : std::hypot(g.dx, g.dy);
+  // MIXED plans: the packed backprojector's per-tile batch bound, measured
+  // once by the backprojector itself with every weight 1 (synchronous)
+  if (precision == DEAM_PREC_MIXED) {
+    if (hipMalloc(&p->d_hbt, (size_t)deam::max_tiles(G) * sizeof(float)) != hipSuccess) {
+      release();
+      return fail(DEAM_ERR_HIP, "hipMalloc of the backprojector bounds failed");
+    }
+    if (deam::launch_bp_bound(p, (float*)p->d_hbt, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess) {
+      release();
+      return fail(DEAM_ERR_HIP, "the backprojector bound pass failed");
+    }
+  }
   *out = p;
   return ok();
 }
@@ -479,6 +495,7 @@ int deam_plan_destroy(deam_plan* plan) {
   if (plan->d_rays) (void)hipFree(plan->d_rays);
   (void)hipFree(plan->d_rays64);
   if (plan->d_bowtie) (void)hipFree(plan->d_bowtie);
+  if (plan->d_hbt) (void)hipFree(plan->d_hbt);
   delete plan;
   return ok();
 }

@@ -208,6 +208,11 @@ struct deam_plan {
   double mu_eff[2][2];
   double mu_eff_inv[2][2];
   void* noalloc;                 // device address of the no-allocation scratch (NULL if unavailable)
+  // MIXED plans: per backprojector tile, a bound of max_x sum_y h(x,y) over
+  // the rays of one view batch, measured by the packed backprojector itself
+  // at plan creation ([max_tiles] float, device), or NULL
+  void* d_hbt;
+  double bp_rays_per_voxel;      // rays of one view that can pass through one voxel (a bound)
 };
 
 namespace deam {
@@ -233,6 +238,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* wmap, hipStream_t st);
 // nonneg: every weight is >= 0 (the AM weights), which allows a cheaper rounding.
 // wmap: the weights' map (from the kernel that wrote them or launch_absmax);
+// The bound pass of the packed backprojector: every weight 1, the plan's own
+// view set; writes per tile a bound of the largest sum of h(x,y) over one
+// view batch into hbt_out [max_tiles] (MIXED plans).
+hipError_t launch_bp_bound(const deam_plan* p, float* hbt_out, hipStream_t st);
 // tmax: per-tile maxima, max_tiles(G) x 4 floats of scratch
 hipError_t launch_backproject(const deam_plan* p, const void* w, int n_ch, bool nonneg,
                               const uint32_t* wmap, float* tmax, void* b, hipStream_t st);

@@ -1395,7 +1395,9 @@ __global__ __launch_bounds__(256) void k_tile_max(GeomDev G, Tiling TL, WMapDev 
 template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
 __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH == 4>())) __attribute__((amdgpu_waves_per_eu(4))) void k_bp(GeomDev G, Tiling TL, const T* __restrict__ w,
                                                  const float* __restrict__ tmax, double h1,
-                                                 double hmax, T* __restrict__ b) {
+                                                 double hmax, T* __restrict__ b,
+                                                 const float* __restrict__ hbt,
+                                                 float* __restrict__ hbt_out, double nterm) {
   // Packed accumulation (float plans, the 4 non-negative AM channels): the
   // LDS word of a voxel holds two channels as 32-bit halves, so one atomic
   // adds two terms.  The scale is chosen so that the sum over one view batch
@@ -1433,16 +1435,21 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
   unsigned long long tot[2 * NOWN];   // PK: 64-bit totals of the owned words
 #pragma unroll
   for (int o = 0; o < 2 * NOWN; ++o) tot[o] = 0ull;
+  uint32_t bmx = 0u;   // bound pass: the largest sum of one batch in an owned word
 
   // h1 bounds max_x sum_y h(x,y) over all views (n_views times a per-view
-  // bound); a batch of VB views contributes at most VB / n_views of it.  The
-  // weight bound m is the tile's own (k_tile_max): the largest |w_c| of the
-  // rays that can meet the tile
-  const double hb = h1 * (double)min(VB, G.nvl) / (double)G.n_views;
+  // bound); a batch of VB views contributes at most VB / n_views of it.
+  // Packed plans have a tighter bound of their own per tile when the views
+  // are the plan's (hbt, measured when the plan was made).  The weight bound
+  // m is the tile's own (k_tile_max): the largest |w_c| of the rays that can
+  // meet the tile.  In the bound pass (hbt_out) every weight is 1.
+  const bool bnd = PK && hbt_out != nullptr;
+  double hb = h1 * (double)min(VB, G.nvl) / (double)G.n_views;
+  if (PK && hbt && !bnd) hb = fmin(hb, (double)hbt[t]);
   T scl[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const float m = tmax[(int64_t)t * 4 + c];
+    const float m = bnd ? 1.f : tmax[(int64_t)t * 4 + c];
     double s;
     if (PK)   // 2^32 - 2^20: room for the +1/2 of every term's rounding and for the FP32
               // roundings of the scaled weights (at most 2^-22 of the bound, 1024)
@@ -1504,7 +1511,7 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
       const int64_t ray = ((int64_t)v * G.n_rows + r) * G.n_cols + k;
       T wa[NCH];   // weight x scale x mm per unit of the driving axis
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) wa[c] = w[c * G.R + ray];
+      for (int c = 0; c < NCH; ++c) wa[c] = bnd ? (T)1 : w[c * G.R + ray];
       Ray<T> ry;
       if (!make_ray<T>(G, rays, v, r, k, tx0, ty0, tz0, tx1, ty1, tz1, ry)) continue;
 #pragma unroll
@@ -1730,11 +1737,31 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
           acc[i] = 0ull;
           tot[2 * o] += (uint32_t)x;
           tot[2 * o + 1] += x >> 32;
+          if (bnd) bmx = max(bmx, max((uint32_t)x, (uint32_t)(x >> 32)));
         }
       }
     }
   }
 
+  if (bnd) {
+    // the tile's largest sum of one batch, in mm: every term was rounded half
+    // up (at most nterm terms per voxel and batch, each at most 1/2 low) and
+    // carries FP32 roundings of at most 2^-22 of its value; the margin
+    // covers both, and the bound never exceeds the geometric one
+    __shared__ uint32_t s_bm[NT / 64];
+    uint32_t m = bmx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+    if ((threadIdx.x & 63) == 0) s_bm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int i = 1; i < NT / 64; ++i) m = max(m, s_bm[i]);
+      const double q = (double)m * (1.0 + 1.0 / 1048576.0) + 0.5 * nterm + 64.0;
+      const double hbx = fmin(q / (double)scl[0] * (1.0 + 1.0 / 1048576.0), hb);
+      hbt_out[t] = (float)hbx;
+    }
+    return;
+  }
   if constexpr (PK) {
 #pragma unroll
     for (int o = 0; o < NOWN; ++o) {
@@ -2463,9 +2490,23 @@ hipError_t launch_absmax(const deam_plan* p, const void* w, int n_ch, uint32_t* 
   return hipGetLastError();
 }
 
+// Bound of the number of terms one voxel receives in one view batch: per view
+// at most nk channels and nr rows pass through it (the factors of the plan's
+// geometric bound), each ray one term, doubled for safety.
+static double batch_terms(const deam_plan* p) {
+  return 2.0 * (double)kViewBatch * p->bp_rays_per_voxel;
+}
+
+// The packed backprojector's per-tile bound applies to the plan's own view
+// set (all views, in order): the batches it was measured on.
+static const float* plan_hbt(const deam_plan* p) {
+  const GeomDev& G = p->gd;
+  return (G.voff == 0 && G.vsub == 1 && G.nvl == G.n_views) ? (const float*)p->d_hbt : nullptr;
+}
+
 template <typename T, bool Z3, int NCH, bool NONNEG, bool SM>
 static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wmap, float* tmax,
-                           void* b, hipStream_t st) {
+                           void* b, hipStream_t st, float* hbt_out = nullptr) {
   using BT = BpTile<Z3, NCH, NONNEG && sizeof(T) == 4 && NCH == 4, SM>;
   Tiling TL{BT::tx, BT::ty, BT::tz, 0, 0, 0};
   TL.ntx = (p->gd.nx + BT::tx - 1) / BT::tx;
@@ -2474,15 +2515,19 @@ static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wm
   const size_t lds = BT::lds_bytes;
   const unsigned nt = (unsigned)(TL.ntx * TL.nty * TL.ntz);
   if ((int64_t)nt > max_tiles(p->gd)) return hipErrorInvalidValue;   // tmax holds max_tiles
-  hipLaunchKernelGGL(k_tile_max, dim3(nt), dim3(256), 0, st, p->gd, TL,
-                     wmap_dev(p->gd, const_cast<uint32_t*>(wmap)), NCH, tmax);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!hbt_out) {   // the bound pass takes every weight as 1 and needs no maxima
+    hipLaunchKernelGGL(k_tile_max, dim3(nt), dim3(256), 0, st, p->gd, TL,
+                       wmap_dev(p->gd, const_cast<uint32_t*>(wmap)), NCH, tmax);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   auto kern = k_bp<T, Z3, NCH, NONNEG, SM>;
   e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nt), dim3(BT::block), lds, st, p->gd, TL, (const T*)w,
-                     (const float*)tmax, p->h1_bound, p->hmax, (T*)b);
+                     (const float*)tmax, p->h1_bound, p->hmax, (T*)b, plan_hbt(p), hbt_out,
+                     batch_terms(p));
   return hipGetLastError();
 }
 
@@ -2490,14 +2535,20 @@ static hipError_t bp_tiles(const deam_plan* p, const void* w, const uint32_t* wm
 // compute unit one, else 16 x 16 tiles (four per CU)
 template <typename T, bool Z3, int NCH, bool NONNEG>
 static hipError_t bp_go(const deam_plan* p, const void* w, const uint32_t* wmap, float* tmax,
-                        void* b, hipStream_t st) {
+                        void* b, hipStream_t st, float* hbt_out = nullptr) {
   if constexpr (Z3) {
-    return bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st);
+    return bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st, hbt_out);
   } else {
     const int64_t n32 = (int64_t)((p->gd.nx + 31) / 32) * ((p->gd.ny + 31) / 32);
-    return n32 >= p->n_cu ? bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st)
-                          : bp_tiles<T, Z3, NCH, NONNEG, true>(p, w, wmap, tmax, b, st);
+    return n32 >= p->n_cu ? bp_tiles<T, Z3, NCH, NONNEG, false>(p, w, wmap, tmax, b, st, hbt_out)
+                          : bp_tiles<T, Z3, NCH, NONNEG, true>(p, w, wmap, tmax, b, st, hbt_out);
   }
+}
+
+hipError_t launch_bp_bound(const deam_plan* p, float* hbt_out, hipStream_t st) {
+  if (p->precision != DEAM_PREC_MIXED) return hipErrorInvalidValue;
+  return p->gd.is3d ? bp_go<float, true, 4, true>(p, nullptr, nullptr, nullptr, nullptr, st, hbt_out)
+                    : bp_go<float, false, 4, true>(p, nullptr, nullptr, nullptr, nullptr, st, hbt_out);
 }
 
 template <typename T, bool Z3>

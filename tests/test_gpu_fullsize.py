@@ -209,16 +209,22 @@ def test_helical_mask_all_rays(helical, helical_trace):
 
 # The packed fixed-point backprojection quantises every term in units of
 # 2^-32 of a bound for one view batch: the largest weight of the rays that can
-# meet the voxel's tile times a bound of one batch's sum of intersection
-# lengths.  Voxels at the two ends of the helix are reached only by the ends
-# of a few chords at the edge of the cone, so their estimated backprojection
-# b^ is 1e-10 to 1e-6 of its maximum: a few quanta (FP32 path) or a few units
-# of 2^-61 of the bound (FP64 path).  Their update, the log of a ratio of such
-# numbers, is not resolved.  Both bounds are asserted on the voxels whose
-# b^_1 and b^_2 (in every iteration compared) are at least RESOLVED times
-# their maximum; the others are counted and reported, and over all voxels a
-# relative L2 ten times the bound is asserted.
-RESOLVED = 1e-6
+# meet the voxel's tile times the tile's largest sum of intersection lengths
+# over a batch (measured when the plan is made).  Voxels at the two ends of
+# the helix are reached only by the ends of a few chords at the edge of the
+# cone, so their estimated backprojection b^ is down to 1e-10 of its
+# maximum: a few quanta (FP32 path) or a few units of 2^-61 of the bound
+# (FP64 path).  Their update, the log of a ratio of such numbers, is not
+# resolved.  Both bounds are asserted on the voxels whose b^_1 and b^_2 (in
+# every iteration compared) are at least RESOLVED[prec] times their maximum;
+# the others are counted and reported, and over all voxels a relative L2 of
+# a tenth of the bound is asserted (the few unresolved voxels weigh little).  FP64 plans scale against the whole scan's
+# geometric bound, not a measured one, so below 1e-6 their voxels reach only
+# about 1e-10.  Over 30 iterations the weakly seen voxels also collect the
+# FP32 roundings of the projections, so that comparison takes voxels at
+# least RESOLVED_30 times the maximum.
+RESOLVED = {"mixed": 1e-8, "fp64": 1e-6}
+RESOLVED_30 = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -226,25 +232,23 @@ def helical_oracle_iterates(helical):
     """The oracle's iterates c^0, c^1, ... and objectives F(c^0), ..., grown on
     demand one iteration at a time (an iteration is deterministic, so
     iterating from c^k once gives c^(k+1))."""
-    return {"c": [helical["c0"]], "h": [], "resolved": [np.ones(helical["c0"].shape[1], bool)],
-            "level": [np.full(helical["c0"].shape[1], np.inf)]}
+    return {"c": [helical["c0"]], "h": [], "level": [np.full(helical["c0"].shape[1], np.inf)]}
 
 
 def oracle_iterate_to(orc, inp, mask_o, state, k):
-    """c^k, F(c^0..c^(k-1)) and the voxels resolved in every iteration so far."""
+    """c^k, F(c^0..c^(k-1)) and each voxel's smallest b^ relative to its
+    maximum (both components) over the iterations so far."""
     while len(state["c"]) <= k:
         t0 = time.time()
         c, h, b = orc.iterate(inp["geom"], inp["I0"], inp["mu"], inp["d"], mask_o, inp["Z"],
                               state["c"][-1], 1, want_b=True)
         bh = b[2:]
         lev = (bh / bh.max(axis=1, keepdims=True)).min(axis=0)   # b^ relative to its maximum
-        ok = lev >= RESOLVED
         state["c"].append(c)
         state["h"].append(float(h[0]))
-        state["resolved"].append(state["resolved"][-1] & ok)
         state["level"].append(np.minimum(state["level"][-1], lev))
         print(f"oracle helical iteration {len(state['c']) - 1}: {time.time() - t0:.1f} s", flush=True)
-    return state["c"][k], np.array(state["h"][:k]), state["resolved"][k], state["level"][k]
+    return state["c"][k], np.array(state["h"][:k]), state["level"][k]
 
 
 @pytest.mark.parametrize("k,prec,tol,htol", [(1, "mixed", 1e-4, 1e-6), (1, "fp64", 1e-10, 1e-10),
@@ -258,7 +262,8 @@ def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_or
     from paper_2202_00116_amd.plan import Plan
     inp = helical
     mask_o, _ = helical_trace
-    c_o, h_o, resolved, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, k)
+    c_o, h_o, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, k)
+    resolved = level >= RESOLVED[prec]
     plan = Plan(inp["geom"], inp["I0"], inp["mu"], prec)
     c = torch.tensor(inp["c0"], device=DEV)
     hist = torch.zeros(k, dtype=torch.float64, device=DEV)
@@ -275,11 +280,11 @@ def test_helical_whole_volume_iterations(orc, helical, helical_trace, helical_or
                   f"{err[sel].max():.3e} of max|c|")
     rest = np.abs(c - c_o)[:, ~resolved]
     print(f"helical {prec}: {int((~resolved).sum())} of {resolved.size} voxels with b^ below "
-          f"{RESOLVED} of its maximum (max error there {rest.max(initial=0.0) / np.abs(c_o).max():.3e}"
+          f"{RESOLVED[prec]} of its maximum (max error there {rest.max(initial=0.0) / np.abs(c_o).max():.3e}"
           f" of max|c|)")
     assert_close(c[:, resolved], c_o[:, resolved], tol,
                  what=f"helical {prec} image after {k} iterations (resolved voxels)")
-    assert_close(c, c_o, 10 * tol, tol_max=np.inf,
+    assert_close(c, c_o, tol / 10, tol_max=np.inf,
                  what=f"helical {prec} image after {k} iterations (all voxels)")
     assert eh <= htol
     del plan
@@ -295,7 +300,8 @@ def test_helical_mixed_tracks_fp64_over_30_iterations(orc, helical, helical_trac
     from paper_2202_00116_amd.plan import Plan
     inp = helical
     mask_o, _ = helical_trace
-    _, _, resolved, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, 1)
+    _, _, level = oracle_iterate_to(orc, inp, mask_o, helical_oracle_iterates, 1)
+    resolved = level >= RESOLVED_30
     n = 30
     d = torch.tensor(inp["d"], device=DEV)
     mask = torch.tensor(mask_o, device=DEV)
@@ -310,7 +316,7 @@ def test_helical_mixed_tracks_fp64_over_30_iterations(orc, helical, helical_trac
         torch.cuda.empty_cache()
     c, c64 = out["mixed"], out["fp64"]
     err = np.abs(c - c64).max(axis=0) / np.abs(c64).max()
-    for lo, hi in ((1e-6, 1e-4), (1e-4, np.inf)):
+    for lo, hi in ((0, 1e-8), (1e-8, 1e-6), (1e-6, 1e-4), (1e-4, np.inf)):
         sel = (level > lo) & (level <= hi)
         print(f"  b^/max in ({lo:.0e}, {hi:.0e}]: {int(sel.sum())} voxels, max error "
               f"{err[sel].max():.3e} of max|c|")

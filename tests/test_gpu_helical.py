@@ -138,4 +138,30 @@ def test_packed_backprojection_weakest_voxels(orc, name):
               f"{b_o[ch][weak].max():.3e}, max b_o {b_o[ch].max():.3e}): max rel {e.max():.3e}, "
               f"median {np.median(e):.3e}")
         worst = max(worst, float(e.max()))
-    assert worst <= 2e-3, worst
+    # relative to each voxel's own sum, which here is down to 4e-5 of the
+    # channel's largest (measured: at most 2.5e-5 on fan512, 4.4e-6 on
+    # helical_mid)
+    assert worst <= 2e-4, worst
+
+
+@pytest.mark.parametrize("name", ["fan64", "fan512", "helical_small", "helical_mid", "random_helix"])
+def test_packed_backprojection_of_ones_at_the_bound(orc, name):
+    """All weights 1 in the packed accumulation: every voxel's sum over a
+    view batch is then its own sum of intersection lengths, and in each tile
+    the largest one meets the per-tile bound the plan measured, which sets
+    the fixed-point scale.  A bound below any batch sum would carry into the
+    neighbouring channel's half of the word (an error of 2^32 quanta); the
+    result must instead match the oracle's backprojection of ones element by
+    element (fan64 takes the 16 x 16 tiles, fan512 the whole-CU ones)."""
+    from paper_2202_00116_amd.plan import Plan
+    from workloads.configs import geometry_for
+    g = random_long_helix(406) if name == "random_helix" else geometry_for(name)
+    I0 = np.array([[1e5], [1e5]])
+    mu = np.array([[0.02], [0.05]])
+    plan = Plan(g, I0, mu, "mixed")
+    w = torch.ones((4, g.n_rays), dtype=torch.float32, device=DEV)
+    b = plan.backproject(w, nonneg=True).cpu().numpy()
+    b_o = orc.backproject(g, np.ones((1, g.n_rays)))[0]
+    for c in range(4):
+        assert_close(b[c], b_o, 1e-5, what=f"{name} packed backprojection of ones, channel {c}")
+    assert np.array_equal(b[0], b[1]) and np.array_equal(b[0], b[2]) and np.array_equal(b[0], b[3])
