@@ -112,7 +112,11 @@ typedef struct deam_plan deam_plan;
  *       energy bin (the I0_j(E) of Eq. 8; no bowtie: the same for every ray);
  *   mu  host [2][n_energy]: basis attenuation mu_i(E) in 1/mm (Eq. 8).
  * Bins where both spectra are zero are dropped (their terms are exactly 0).
- * precision: deam_precision.  Copies the tables to the current device. */
+ * precision: deam_precision.  Copies the tables to the current device; a
+ * MIXED plan also measures, with one backprojection pass of unit weights on
+ * the default stream (synchronous), a per-tile bound of one view batch's sum
+ * of intersection lengths, which sets the fixed-point scale of the packed
+ * backprojection (deam_iterate, DEAM_BP_NONNEG with 4 channels). */
 int deam_plan_create(const deam_geometry* geom, int32_t n_energy, const double* I0,
                      const double* mu, int32_t precision, deam_plan** out);
 int deam_plan_destroy(deam_plan* plan);
