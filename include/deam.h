@@ -184,7 +184,7 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
 /* deam_poly_mean for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments without the workspace, the same results bit for bit.
- * Its scratch (the per-block objective partials and the weight maxima) is a
+ * Its scratch (the per-block objective partials) is a
  * fixed device array of the library, 2 MiB per GPU, held until the process
  * ends; it serves at most 67 100 672 rays (R larger returns
  * DEAM_ERR_UNSUPPORTED, enqueuing nothing).  The call allocates nothing and

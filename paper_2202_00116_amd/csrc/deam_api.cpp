@@ -202,11 +202,9 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       break;
     case DEAM_OP_POLY_MEAN:
       L.partial = take((size_t)p->ray_blocks * 8);
-      L.wmax = take(64);
       L.scratch = take(64);
       break;
     case DEAM_OP_BACKPROJECT:
-      L.wmax = take(64);
       take_bp_maps();
       break;
     case DEAM_OP_ITERATE_VJP:
@@ -219,7 +217,6 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.lam = take(R * 2 * rs);
       L.bl = take(V * 2 * rs);
       L.partial = take((size_t)p->ray_blocks * 8);
-      L.wmax = take(64);
       take_bp_maps();
       break;
     case DEAM_OP_PENALTY:
@@ -232,7 +229,6 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.c_prev = take(V * 2 * 8);
       // projector partials, then (contiguous) penalty partials: one reduction
       L.partial = take((nblk + (size_t)pen_blocks(p)) * 8);
-      L.wmax = take(64);
       L.scratch = take(64);
       take_bp_maps();
       break;
@@ -255,7 +251,6 @@ WsLayout workspace_layout(const deam_plan* p, int op) {
       L.w = take(R * 4 * rs);
       L.b = take(V * 4 * rs);
       L.partial = take(nblk * 8);
-      L.wmax = take(64);
       L.scratch = take(64);
       take_bp_maps();
       break;
@@ -614,10 +609,8 @@ int deam_poly_mean(const deam_plan* plan, const void* l, const float* d, const u
                  : mode == DEAM_W_GRAD ? deam::PM_GRAD
                  : mode == DEAM_W_VJP  ? deam::PM_VJP
                                        : deam::PM_STEP;
-  uint32_t* wmax = (uint32_t*)(wsb + L.wmax);
   double* partial = (double*)(wsb + L.partial);
-  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
+  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, st));
   if (obj) HIP_TRY(deam::launch_reduce(partial, plan->ray_blocks, obj, st));
   return ok();
 }
@@ -648,12 +641,9 @@ int deam_poly_mean_noalloc(const deam_plan* plan, const void* l, const float* d,
                  : mode == DEAM_W_VJP  ? deam::PM_VJP
                                        : deam::PM_STEP;
   char* s = (char*)plan->noalloc;
-  uint32_t* wmax = (uint32_t*)s;
   double* partial = (double*)(s + deam::kNoAllocPartialOffset);
-  // the maxima start at zero (a fill kernel, no memset node); the kernel
-  // writes every partial it reduces
-  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, wmax, st));
+  // the kernel writes every partial it reduces (nothing to clear)
+  HIP_TRY(deam::launch_poly(plan, l, d, mask, pm, v, w, g, partial, st));
   if (obj) HIP_TRY(deam::launch_reduce(partial, plan->ray_blocks, obj, st));
   return ok();
 }
@@ -747,7 +737,6 @@ static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const 
   hipStream_t st = (hipStream_t)stream;
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
-  uint32_t* wmax = (uint32_t*)(w + L.wmax);
   uint32_t* wmap = (uint32_t*)(w + L.wmap);
   float* tmax = (float*)(w + L.tmax);
   const int64_t nmap = deam::wmap_words(plan->gd);
@@ -784,10 +773,9 @@ static int iterate_impl(const deam_plan* plan, double* c64, void* c_proj, const 
                            cpx, st));
   STEP(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
-    STEP(deam::launch_fill_u32(wmax, 0u, 16, st));
     STEP(deam::launch_fill_u32(wmap, 0u, nmap, st));
     STEP(mark(k, 0));
-    STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st,
+    STEP(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, st,
                               wmap));
     STEP(mark(k, 1));
     if (obj_hist) {
@@ -1030,7 +1018,6 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
   hipStream_t st = (hipStream_t)stream;
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
-  uint32_t* wmax = (uint32_t*)(w + L.wmax);
   uint32_t* wmap = (uint32_t*)(w + L.wmap);
   float* tmax = (float*)(w + L.tmax);
   const int64_t nmap = deam::wmap_words(plan->gd);
@@ -1039,15 +1026,13 @@ int deam_iterate_os(const deam_plan* plan, double* c64, const float* d, const ui
   HIP_TRY(deam::launch_zero_tail(plan, cpx, plan->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
     if (obj_hist) {  // the objective needs every view at the epoch's iterate
-      HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-      HIP_TRY(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st));
+          HIP_TRY(deam::launch_fp_poly(plan, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, st));
       HIP_TRY(deam::launch_reduce(partial, plan->fp_blocks, obj_hist + k, st));
     }
     for (int s = 0; s < n_sub; ++s) {
       const deam_plan sub = subset_plan(plan, n_sub, s);
-      HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
-      HIP_TRY(deam::launch_fill_u32(wmap, 0u, nmap, st));
-      HIP_TRY(deam::launch_fp_poly(&sub, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, wmax, st,
+          HIP_TRY(deam::launch_fill_u32(wmap, 0u, nmap, st));
+      HIP_TRY(deam::launch_fp_poly(&sub, cpy, cpx, d, mask, deam::PM_AM, w + L.w, partial, st,
                                    wmap));
       HIP_TRY(deam::launch_backproject(&sub, w + L.w, 4, true, wmap, tmax, w + L.b, st));
       HIP_TRY(deam::launch_update(plan, c64, w + L.b, Z[0], Z[1], nullptr, cpy, cpx, st));
@@ -1100,8 +1085,6 @@ int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double
   // one packed copy of c serves both scans (same image grid)
   void* cpy = wa + LA.cp_y;
   void* cpx = wa + LA.cp_x;
-  uint32_t* wmax_a = (uint32_t*)(wa + LA.wmax);
-  uint32_t* wmax_b = (uint32_t*)(wb + LB.wmax);
   uint32_t* wmap_a = (uint32_t*)(wa + LA.wmap);
   uint32_t* wmap_b = (uint32_t*)(wb + LB.wmap);
   float* tmax_a = (float*)(wa + LA.tmax);
@@ -1112,14 +1095,12 @@ int deam_iterate_dual(const deam_plan* plan_lo, const deam_plan* plan_hi, double
   HIP_TRY(deam::launch_update(plan_lo, c64, nullptr, Z[0], Z[1], nullptr, cpy, cpx, st));
   HIP_TRY(deam::launch_zero_tail(plan_lo, cpx, plan_lo->precision == DEAM_PREC_FP64, st));
   for (int k = 0; k < n_iter; ++k) {
-    HIP_TRY(deam::launch_fill_u32(wmax_a, 0u, 16, st));
-    HIP_TRY(deam::launch_fill_u32(wmax_b, 0u, 16, st));
     HIP_TRY(deam::launch_fill_u32(wmap_a, 0u, deam::wmap_words(plan_lo->gd), st));
     HIP_TRY(deam::launch_fill_u32(wmap_b, 0u, deam::wmap_words(plan_hi->gd), st));
     HIP_TRY(deam::launch_fp_poly(plan_lo, cpy, cpx, d_lo, mask_lo, deam::PM_AM, wa + LA.w, part_a,
-                                 wmax_a, st, wmap_a));
+                                 st, wmap_a));
     HIP_TRY(deam::launch_fp_poly(plan_hi, cpy, cpx, d_hi, mask_hi, deam::PM_AM, wb + LB.w, part_b,
-                                 wmax_b, st, wmap_b));
+                                 st, wmap_b));
     if (obj_hist) {
       HIP_TRY(deam::launch_reduce(part_a, plan_lo->fp_blocks, two, st));
       HIP_TRY(deam::launch_reduce(part_b, plan_hi->fp_blocks, two + 1, st));
@@ -1150,7 +1131,6 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   const size_t V = (size_t)plan->gd.V, R = (size_t)plan->gd.R;
   void* cpy = w + L.cp_y;
   void* cpx = w + L.cp_x;
-  uint32_t* wmax = (uint32_t*)(w + L.wmax);
   uint32_t* wmap = (uint32_t*)(w + L.wmap);
   float* tmax = (float*)(w + L.tmax);
   double* partial = (double*)(w + L.partial);
@@ -1159,10 +1139,9 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
                               cpx, st));
   HIP_TRY(deam::launch_zero_tail(plan, cpx, dbl, st));
   HIP_TRY(deam::launch_forward(plan, cpy, cpx, w + L.l, 2, st));
-  HIP_TRY(deam::launch_fill_u32(wmax, 0u, 16, st));
   HIP_TRY(deam::launch_fill_u32(wmap, 0u, deam::wmap_words(plan->gd), st));
   HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_AM, nullptr, w + L.w, nullptr,
-                            partial, wmax, st, wmap));
+                            partial, st, wmap));
   HIP_TRY(deam::launch_backproject(plan, w + L.w, 4, true, wmap, tmax, w + L.b, st));
   // upstream images for b~ and b^, and their projections alpha = H u~, beta = H u^
   HIP_TRY(deam::launch_step_u(plan, G, w + L.b, Z[0], Z[1], w + L.u, st));
@@ -1172,7 +1151,7 @@ int deam_iterate_vjp(const deam_plan* plan, const double* c64, const float* d,
   }
   // lambda per ray, then out = G + H^T lambda
   HIP_TRY(deam::launch_poly(plan, w + L.l, d, mask, deam::PM_STEP, w + L.ab, w + L.lam, nullptr,
-                            partial, nullptr, st));
+                            partial, st));
   HIP_TRY(deam::launch_absmax(plan, w + L.lam, 2, wmap, st));
   HIP_TRY(deam::launch_backproject(plan, w + L.lam, 2, false, wmap, tmax, w + L.bl, st));
   HIP_TRY(deam::launch_add_g(plan, G, w + L.bl, out, st));

@@ -117,8 +117,8 @@ constexpr int kViewBatch = 128;
 constexpr int kMaxFbpCols = 4096;   // FBP filter: one detector row of p and g in LDS (64 KiB)
 
 // Device scratch of deam_poly_mean_noalloc (a file-scope array of the kernel
-// library, one copy per GPU): 256 bytes of per-channel weight maxima, then
-// the FP64 per-block partial sums of the objective.
+// library, one copy per GPU): the FP64 per-block partial sums of the
+// objective, from byte kNoAllocPartialOffset.
 constexpr size_t kNoAllocScratchBytes = (size_t)2 << 20;
 constexpr size_t kNoAllocPartialOffset = 256;
 
@@ -169,7 +169,6 @@ struct WsLayout {
   size_t w;              // per-ray weights
   size_t b;              // back-projections
   size_t partial;        // per-block FP64 partial sums
-  size_t wmax;           // per-channel max |w| (uint32 float bits)
   size_t wmap, tmax;     // weight-maxima map and per-tile maxima (backprojection)
   size_t scratch;        // small FP64 scratch
   size_t l, u, ab, lam, bl;   // iteration VJP: line integrals, upstream images, their
@@ -228,9 +227,9 @@ hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* 
 // wmap (or NULL): the weight-maxima map, which must hold zeros before
 hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
                           const uint8_t* mask, int mode, void* w, double* partial,
-                          uint32_t* wmax, hipStream_t st, uint32_t* wmap = nullptr);
+                          hipStream_t st, uint32_t* wmap = nullptr);
 hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
-                       int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
+                       int mode, const void* v, void* w, void* g, double* partial,
                        hipStream_t st, uint32_t* wmap = nullptr);
 hipError_t launch_reduce(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

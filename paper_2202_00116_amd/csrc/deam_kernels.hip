@@ -740,39 +740,22 @@ __device__ __forceinline__ int64_t map_entry(const WMapDev& M, int v, int r, int
   return ((int64_t)v * M.ngm + r / kMapRows) * M.nkb + k / kMapCols;
 }
 
-// Block reductions: FP64 sum into partial[lb], float max into wmax (atomicMax
-// on the bit pattern, valid for non-negative values), and the map entry of
-// each lane's ray.
+// Block reduction of the FP64 objective terms into partial[lb] (a fixed
+// order), and the map entry of each lane's ray.
 template <int NW, int NT = kFpBlock>
 __device__ void block_reduce(double term, const float wabs[4], int nch, double* partial, int lb,
-                             uint32_t* wmax, const WMapDev& M = WMapDev{}, int64_t entry = 0,
-                             bool valid = false) {
+                             const WMapDev& M = WMapDev{}, int64_t entry = 0, bool valid = false) {
   map_update(M, entry, wabs, nch, valid);
   __shared__ double s_sum[NT / 64];
-  __shared__ float s_max[NT / 64][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  float m[4] = {wabs[0], wabs[1], wabs[2], wabs[3]};
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    term += __shfl_xor(term, o);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) m[c] = fmaxf(m[c], __shfl_xor(m[c], o));
-  }
-  if (lane == 0) {
-    s_sum[wv] = term;
-    for (int c = 0; c < 4; ++c) s_max[wv][c] = m[c];
-  }
+  for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
+  if (lane == 0) s_sum[wv] = term;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    float mm[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int i = 0; i < NT / 64; ++i) {
-      s += s_sum[i];
-      for (int c = 0; c < 4; ++c) mm[c] = fmaxf(mm[c], s_max[i][c]);
-    }
-    if (partial) partial[lb] = s;
-    if (wmax)
-      for (int c = 0; c < nch; ++c) atomicMax(&wmax[c], __float_as_uint(mm[c]));
+    double sum = 0.0;
+    for (int i = 0; i < NT / 64; ++i) sum += s_sum[i];
+    if (partial) partial[lb] = sum;
   }
 }
 
@@ -785,7 +768,7 @@ __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof
     GeomDev G, const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff,
     const EBin<T>* __restrict__ eb, int nE,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
-    double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
+    double* __restrict__ partial, double tthr,
     uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout, WMapDev M) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   // rays of the walked views, channel fastest; `ray` is the index in the
@@ -825,7 +808,7 @@ __global__ __launch_bounds__(kFpBlock) __attribute__((amdgpu_waves_per_eu(sizeof
   }
   if constexpr (MODE == PM_AM || MODE == PM_GRAD) {
     const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
-    block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax, M, entry, active);
+    block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, M, entry, active);
   }
 }
 
@@ -853,7 +836,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
     GeomDev G, const typename Vec2<T>::type* __restrict__ cp, uint32_t xoff,
     const EBin<T>* __restrict__ eb, int nE,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, T* __restrict__ out,
-    double* __restrict__ partial, uint32_t* __restrict__ wmax, double tthr,
+    double* __restrict__ partial, double tthr,
     uint8_t* __restrict__ mask_out, double* __restrict__ Tout, int nout, WMapDev M) {
   using T2 = typename Vec2<T>::type;
   constexpr uint32_t E = sizeof(T2);
@@ -1118,7 +1101,7 @@ __global__ __launch_bounds__(64 * kFp3Views) void k_fp3(
     const float wf[4] = {(float)wabs[0], (float)wabs[1], (float)wabs[2], (float)wabs[3]};
     // the lane's rows r0 .. r0 + RG - 1 lie in one group of the map (RG divides it)
     static_assert(kMapRows % RG == 0, "row groups of the map hold whole row groups of the walk");
-    block_reduce<4, 64 * kFp3Views>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, wmax, M,
+    block_reduce<4, 64 * kFp3Views>(term, wf, MODE == PM_AM ? 4 : 2, partial, lb, M,
                                      map_entry(M, v, r0, k), valid);
   }
 }
@@ -1128,7 +1111,7 @@ __global__ __launch_bounds__(kFpBlock) void k_poly(
     int64_t R, const EBin<T>* __restrict__ eb, int nE, const T* __restrict__ l,
     const float* __restrict__ d, const uint8_t* __restrict__ mask, const T* __restrict__ v,
     T* __restrict__ w, T* __restrict__ gout, double* __restrict__ partial,
-    uint32_t* __restrict__ wmax, int n_cols, const T* __restrict__ bt, WMapDev M) {
+    int n_cols, const T* __restrict__ bt, WMapDev M) {
   const int64_t ray = (int64_t)blockIdx.x * kFpBlock + threadIdx.x;
   double term = 0.0;
   T wabs[4] = {0, 0, 0, 0};
@@ -1146,7 +1129,7 @@ __global__ __launch_bounds__(kFpBlock) void k_poly(
   const int64_t vr = rr / M.n_cols;
   const int64_t entry =
       map_entry(M, (int)(vr / M.n_rows), (int)(vr % M.n_rows), (int)(rr % M.n_cols));
-  block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, wmax, M, entry, ray < R);
+  block_reduce<4>(term, wf, MODE == PM_AM ? 4 : 2, partial, blockIdx.x, M, entry, ray < R);
 }
 
 // max |w_c| over rays, per channel (for the fixed-point scale of a
@@ -2374,7 +2357,7 @@ hipError_t launch_zero_tail(const deam_plan* p, void* cp_x, bool dbl, hipStream_
 
 template <typename T, int MODE>
 static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
-                        const uint8_t* mask, void* out, double* partial, uint32_t* wmax,
+                        const uint8_t* mask, void* out, double* partial,
                         double tthr, uint8_t* mask_out, double* Tout, hipStream_t st, int nout = 2,
                         uint32_t* wmap = nullptr) {
   using T2 = typename Vec2<T>::type;
@@ -2388,40 +2371,40 @@ static void fp_dispatch(const deam_plan* p, const void* cp_y, const void* cp_x, 
     const dim3 grid3((unsigned)fp3_blocks(p->gd.nvl, p->gd.n_rows, p->gd.n_cols, RG));
     hipLaunchKernelGGL((k_fp3<T, MODE, RG>), grid3, dim3(64 * kFp3Views), 0, st, p->gd,
                        (const T2*)cp_y, xoff,
-                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout, M);
+                       eb, p->nE, d, mask, (T*)out, partial, tthr, mask_out, Tout, nout, M);
   } else
     hipLaunchKernelGGL((k_fp<T, false, MODE>), grid, blk, 0, st, p->gd, (const T2*)cp_y, xoff,
-                       eb, p->nE, d, mask, (T*)out, partial, wmax, tthr, mask_out, Tout, nout, M);
+                       eb, p->nE, d, mask, (T*)out, partial, tthr, mask_out, Tout, nout, M);
 }
 
 hipError_t launch_forward(const deam_plan* p, const void* cp_y, const void* cp_x, void* l,
                           int n_out, hipStream_t st) {
   if (p->precision == DEAM_PREC_FP64)
-    fp_dispatch<double, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, nullptr, 0.0, nullptr,
+    fp_dispatch<double, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, 0.0, nullptr,
                               nullptr, st, n_out);
   else
-    fp_dispatch<float, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, nullptr, 0.0, nullptr,
+    fp_dispatch<float, PM_L>(p, cp_y, cp_x, nullptr, nullptr, l, nullptr, 0.0, nullptr,
                              nullptr, st, n_out);
   return hipGetLastError();
 }
 
 hipError_t launch_metal_trace(const deam_plan* p, const void* cp_y, const void* cp_x, double t,
                               uint8_t* mask, double* T, hipStream_t st) {
-  fp_dispatch<double, PM_TRACE>(p, cp_y, cp_x, nullptr, nullptr, nullptr, nullptr, nullptr, t,
+  fp_dispatch<double, PM_TRACE>(p, cp_y, cp_x, nullptr, nullptr, nullptr, nullptr, t,
                                 mask, T, st);
   return hipGetLastError();
 }
 
 hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x, const float* d,
                           const uint8_t* mask, int mode, void* w, double* partial,
-                          uint32_t* wmax, hipStream_t st, uint32_t* wmap) {
+                          hipStream_t st, uint32_t* wmap) {
   const bool dbl = p->precision == DEAM_PREC_FP64;
   if (mode == PM_AM) {
-    if (dbl) fp_dispatch<double, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
-    else fp_dispatch<float, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
+    if (dbl) fp_dispatch<double, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, 0, nullptr, nullptr, st, 2, wmap);
+    else fp_dispatch<float, PM_AM>(p, cp_y, cp_x, d, mask, w, partial, 0, nullptr, nullptr, st, 2, wmap);
   } else if (mode == PM_GRAD) {
-    if (dbl) fp_dispatch<double, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
-    else fp_dispatch<float, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, wmax, 0, nullptr, nullptr, st, 2, wmap);
+    if (dbl) fp_dispatch<double, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, 0, nullptr, nullptr, st, 2, wmap);
+    else fp_dispatch<float, PM_GRAD>(p, cp_y, cp_x, d, mask, w, partial, 0, nullptr, nullptr, st, 2, wmap);
   } else {
     return hipErrorInvalidValue;
   }
@@ -2431,36 +2414,36 @@ hipError_t launch_fp_poly(const deam_plan* p, const void* cp_y, const void* cp_x
 template <typename T>
 static void poly_dispatch(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
                           int mode, const void* v, void* w, void* g, double* partial,
-                          uint32_t* wmax, hipStream_t st, uint32_t* wmap) {
+                          hipStream_t st, uint32_t* wmap) {
   const int64_t R = p->gd.R;
   const WMapDev M = wmap_dev(p->gd, wmap);
   const dim3 grid((unsigned)((R + kFpBlock - 1) / kFpBlock)), blk(kFpBlock);
   const EBin<T>* eb = (const EBin<T>*)p->d_energy;
   if (mode == PM_AM)
     hipLaunchKernelGGL((k_poly<T, PM_AM>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)v, (T*)w, (T*)g, partial, p->gd.n_cols,
                        (const T*)p->gd.bowtie, M);
   else if (mode == PM_GRAD)
     hipLaunchKernelGGL((k_poly<T, PM_GRAD>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d,
-                       mask, (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       mask, (const T*)v, (T*)w, (T*)g, partial, p->gd.n_cols,
                        (const T*)p->gd.bowtie, M);
   else if (mode == PM_VJP)
     hipLaunchKernelGGL((k_poly<T, PM_VJP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)v, (T*)w, (T*)g, partial, p->gd.n_cols,
                        (const T*)p->gd.bowtie, M);
   else
     hipLaunchKernelGGL((k_poly<T, PM_STEP>), grid, blk, 0, st, R, eb, p->nE, (const T*)l, d, mask,
-                       (const T*)v, (T*)w, (T*)g, partial, wmax, p->gd.n_cols,
+                       (const T*)v, (T*)w, (T*)g, partial, p->gd.n_cols,
                        (const T*)p->gd.bowtie, M);
 }
 
 hipError_t launch_poly(const deam_plan* p, const void* l, const float* d, const uint8_t* mask,
-                       int mode, const void* v, void* w, void* g, double* partial, uint32_t* wmax,
+                       int mode, const void* v, void* w, void* g, double* partial,
                        hipStream_t st, uint32_t* wmap) {
   if (p->precision == DEAM_PREC_FP64)
-    poly_dispatch<double>(p, l, d, mask, mode, v, w, g, partial, wmax, st, wmap);
+    poly_dispatch<double>(p, l, d, mask, mode, v, w, g, partial, st, wmap);
   else
-    poly_dispatch<float>(p, l, d, mask, mode, v, w, g, partial, wmax, st, wmap);
+    poly_dispatch<float>(p, l, d, mask, mode, v, w, g, partial, st, wmap);
   return hipGetLastError();
 }
 
