@@ -36,9 +36,6 @@
 // copy, so calls that overlap on one GPU race.
 static __device__ __align__(256) unsigned char scratch[deam::kNoAllocScratchBytes];
 
-#ifndef DEAM_BP_INCREMENTAL
-#define DEAM_BP_INCREMENTAL 1
-#endif
 
 namespace deam {
 namespace {
@@ -1616,9 +1613,8 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
         bp = bn;
       };
       // a full step [fa, fa + 1] inside one slice (DEP), or one that crosses
-      // a slice plane and only advances the in-plane state (!DEP)
-#if DEAM_BP_INCREMENTAL
-      // Full steps in Siddon's incremental form: e is the distance (in plane
+      // a slice plane and only advances the in-plane state (!DEP), in
+      // Siddon's incremental form: e is the distance (in plane
       // spacings) from the start of the step to the next lateral plane.  A
       // step with e < 1 splits there and moves one pixel in the direction sg,
       // and e grows by 1/|mb| - 1, otherwise it falls by 1 (exact).  Only the
@@ -1648,36 +1644,13 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
         row8 += 8 * sa;
         A = B;
       };
-#else
-      auto fstep = [&](auto dep) {
-        fa += (T)1;
-        const T bn = fma(fa, ry.mb, ry.b0);
-        const int B = clampi(ifloor(bn), lbb, hb - 1);
-        if constexpr (decltype(dep)::value) {
-          const T dA = (B == A) ? (T)1 : clamp0(((T)max(A, B) - bp) * ry.imb, (T)1);
-          QT qa[NCH];
-          quant(dA, qa);
-          add(__mul24(A, sb8) + row8, qa);
-          if (B != A) {
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) qa[c] = LQ[c] - qa[c];
-            add(__mul24(B, sb8) + row8, qa);
-          }
-        }
-        row8 += 8 * sa;
-        A = B;
-        bp = bn;
-      };
-#endif
       if (q0 < q1) {
         gstep(q0);
         const int ql = q1 - 1;     // the last step (partial) is gstep's
         int q = q0 + 1;
-#if DEAM_BP_INCREMENTAL
         // the distance to the next lateral plane from the line at the start
         // of the first full step
         e = sg > 0 ? ((T)(A + 1) - bp) * iab : (sg < 0 ? (bp - (T)A) * iab : (T)1e30);
-#endif
         while (q < ql) {
           // full steps up to the next slice crossing, then the crossing step
           const int qe = min(qc, ql);
@@ -1689,11 +1662,9 @@ __global__ __launch_bounds__((bp_block<Z3, SM, NONNEG && sizeof(T) == 4 && NCH =
           }
         }
         tp = fa;   // the last step starts on a plane
-#if DEAM_BP_INCREMENTAL
         // back to the line for the last (partial) step
         bp = fma(fa, ry.mb, ry.b0);
         A = clampi(ifloor(bp), lbb, hb - 1);
-#endif
         if (ql > q0) gstep(ql);
       }
       if constexpr (Z3) {
